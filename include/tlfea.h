@@ -1,0 +1,177 @@
+/*
+ * tlfea.h -- C ABI of the MI355X (gfx950) Total Lagrangian internal-force
+ * library.
+ *
+ * The library evaluates, for every element and quadrature point of a mesh,
+ * the deformation gradient F = sum_a x_a h_a^T (Sec. 2.1, compact map
+ * r = N s and F = N H), the first Piola-Kirchhoff stress P = dpsi/dF of a
+ * St. Venant-Kirchhoff or Mooney-Rivlin / Neo-Hookean law plus the
+ * Kelvin-Voigt viscous stress F S_v(Edot) (Sec. 3.2), and assembles the nodal
+ * internal forces f_a = int P h_a dV_r (Sec. 4.3, the constitutive-
+ * discretisation interface) by parent-element quadrature with the
+ * isoparametric chain rule h_a^T = ds_a/dxi [U G]^{-1}, J_p = det(U G) > 0
+ * (Sec. 6).  It also provides the adjoint (vector-Jacobian) product of f with
+ * respect to nodal positions, velocities and per-element material parameters,
+ * and the tangent product (df/dx) dx + (df/dv) dv, whose element blocks are
+ * the consistent linearisations of App. C (plus the Kelvin-Voigt blocks,
+ * which the paper does not print).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Floating point is IEEE binary64 throughout; indices are int32.
+ * - Nodal arrays (X, x, v, f, w, gx, gv, dx, dv, df) are structure-of-arrays
+ *   [3][n_nodes]: component c of node n is at [c * n_nodes + n].  These are
+ *   the rows of the paper's N(t) (Sec. 2.1).
+ * - Per-element parameter arrays (theta, gtheta) are [5][n_elem] in the
+ *   caller's element order (blocks concatenated in creation order).  Rows:
+ *     SVK : (lambda, mu, unused, mu_v, lambda_v)          (Sec. 3.2.1/3.2.3)
+ *     MR  : (mu10, mu01, k, mu_v, lambda_v)               (Sec. 3.2.2/3.2.3)
+ *     NH  : (mu10, unused, k, mu_v, lambda_v); Mooney-Rivlin with mu01 = 0.
+ *   Rows marked unused, and rows 3-4 of an undamped block, are ignored on
+ *   input and written as 0 in gtheta.
+ * - tlfea_create_mesh takes HOST pointers and copies everything it keeps;
+ *   the compute calls take DEVICE pointers (memory of the device that was
+ *   current at creation) and a hipStream_t passed as void* (NULL = the null
+ *   stream).  Compute calls only enqueue work and return; results are ready
+ *   when the stream reaches that point.
+ * - Outputs are overwritten, never accumulated, and must not alias inputs.
+ * - A mesh holds device scratch for partial node sums: calls on one mesh must
+ *   not overlap in time (issue them on one stream, or synchronise).
+ * - Every function returns a tlfea_status; nothing throws.  On a non-OK
+ *   status tlfea_last_error() gives a message (thread-local).  Argument
+ *   checks happen on the host before any device work is enqueued.
+ */
+#ifndef TLFEA_H
+#define TLFEA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tlfea_mesh tlfea_mesh;   /* opaque, immutable geometry */
+
+typedef enum {
+    TLFEA_OK = 0,
+    TLFEA_E_INVALID = -1,        /* null pointer, unknown enum or flag        */
+    TLFEA_E_SHAPE = -2,          /* inconsistent sizes, node id out of range  */
+    TLFEA_E_REF_JACOBIAN = -3,   /* J_p <= 0 at a quadrature point (Sec. 6)   */
+    TLFEA_E_NOMEM = -4,          /* host or device allocation failed          */
+    TLFEA_E_DEVICE = -5,         /* HIP runtime error (also a prior fault)    */
+    TLFEA_E_UNSUPPORTED = -6     /* valid request this build does not handle  */
+} tlfea_status;
+
+enum { TLFEA_T10 = 0, TLFEA_H8 = 1 };          /* element types            */
+enum { TLFEA_SVK = 0, TLFEA_MR = 1, TLFEA_NH = 2 };  /* constitutive laws  */
+enum { TLFEA_NPAR = 5 };                         /* parameter rows          */
+
+/* tlfea_create_mesh flags (bitwise or) */
+enum {
+    TLFEA_PLAIN = 0,
+    TLFEA_BATCHED = 1,      /* replay each call's launches as one hipGraph    */
+    TLFEA_AUTOTUNE = 2,     /* time candidate tile sizes at creation          */
+    TLFEA_KEEP_ORDER = 4    /* keep the caller's element order (no reorder)  */
+};
+
+/*
+ * One block: elements of one type and one law (one body, or a part of one).
+ * T10 node order follows the paper's node table (App. A, 10-node
+ * tetrahedron): corners at parent (0,0,0), (1,0,0), (0,1,0), (0,0,1), then
+ * mid-edge nodes 1-2, 2-3, 1-3, 1-4, 2-4, 3-4.  H8 (not in the paper) is the
+ * trilinear hexahedron on [-1,1]^3 with nodes in the paper's Q27 convention
+ * (lexicographic, i fastest).  Quadrature: T10 5-point degree-3 rule, H8
+ * 2x2x2 Gauss.
+ */
+typedef struct {
+    int32_t elem;            /* TLFEA_T10 or TLFEA_H8                          */
+    int32_t law;             /* TLFEA_SVK, TLFEA_MR or TLFEA_NH                */
+    int64_t n_elem;          /* elements in this block, >= 0                   */
+    const int32_t *conn;     /* HOST [n_elem][nen], 0-based global node ids    */
+    double theta[5];         /* default parameter rows (used when theta==NULL) */
+    int32_t damped;          /* nonzero: Kelvin-Voigt branch active            */
+    int32_t tile_elems;      /* elements per tile: 0 = default, else 64/128/256*/
+} tlfea_block;
+
+typedef struct {
+    int64_t n_nodes, n_elem, n_qp;
+    int64_t n_tiles, n_halo_nodes, n_partials;
+    int32_t n_blocks, flags;
+    int32_t tile_elems_t10, tile_elems_h8;   /* chosen (autotuned) tile sizes  */
+    int64_t device_bytes;                    /* device memory the mesh holds   */
+} tlfea_mesh_info;
+
+/*
+ * Build a mesh on the current HIP device.  X_ref is HOST [3][n_nodes]
+ * (reference nodes U, Sec. 6); blocks[b].conn is HOST.  Validation (ids in
+ * range, finite coordinates, J_p > 0 at every quadrature point of every
+ * element) runs on the host before any device allocation; failures return
+ * TLFEA_E_SHAPE / TLFEA_E_REF_JACOBIAN / TLFEA_E_INVALID and leave *out NULL.
+ * The mesh reorders elements along a Morton curve (unless TLFEA_KEEP_ORDER)
+ * and cuts them into tiles; this never changes the caller-visible order of
+ * theta / gtheta.  Ownership: the caller keeps its inputs; release the mesh
+ * with tlfea_destroy_mesh.
+ */
+tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X_ref, int32_t n_blocks,
+                               const tlfea_block *blocks, int32_t flags, tlfea_mesh **out);
+
+/* Free the mesh and its device memory (NULL is a no-op).  Synchronises the
+ * device first so no enqueued call still uses it. */
+void tlfea_destroy_mesh(tlfea_mesh *mesh);
+
+/* Sizes and the tiling the mesh chose. */
+tlfea_status tlfea_get_mesh_info(const tlfea_mesh *mesh, tlfea_mesh_info *info);
+
+/*
+ * Internal force f = f_int(x, v) (Sec. 4.3, f_i = int P h_i dV_r; with
+ * Kelvin-Voigt f = f^e + f^v).  x: DEVICE [3][n_nodes] current positions
+ * (Sec. 2.1, columns of N(t)); v: DEVICE [3][n_nodes] velocities (columns of
+ * Ndot), may be NULL when no block is damped; theta: DEVICE [5][n_elem] or
+ * NULL for the blocks' defaults; f: DEVICE [3][n_nodes], overwritten (nodes
+ * no element touches get 0).  Sign: f enters the residual with +
+ * (Sec. 7), i.e. f = +dPi/dx.
+ */
+tlfea_status tlfea_internal_force(tlfea_mesh *mesh, const double *x, const double *v,
+                                  const double *theta, double *f, void *stream);
+
+/*
+ * Adjoint product of the internal force for a cotangent w (DEVICE [3][n_nodes]):
+ *   gx = (df/dx)^T w, gv = (df/dv)^T w   (DEVICE [3][n_nodes], each may be NULL)
+ *   gtheta[p][e] = w . df/dtheta[p][e]   (DEVICE [5][n_elem], may be NULL)
+ * The element blocks are those of App. C; F is recomputed from x, not stored.
+ * For undamped blocks gv gets no contribution.
+ */
+tlfea_status tlfea_internal_force_vjp(tlfea_mesh *mesh, const double *x, const double *v,
+                                      const double *theta, const double *w, double *gx,
+                                      double *gv, double *gtheta, void *stream);
+
+/*
+ * Tangent product df = (df/dx) dx + (df/dv) dv (App. C consistent
+ * linearisation, K_t = df_int/dq of Sec. 7, plus the Kelvin-Voigt blocks).
+ * dx, dv: DEVICE [3][n_nodes] or NULL (treated as zero); df overwritten.
+ */
+tlfea_status tlfea_tangent_jvp(tlfea_mesh *mesh, const double *x, const double *v,
+                               const double *theta, const double *dx, const double *dv,
+                               double *df, void *stream);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *tlfea_last_error(void);
+
+/*
+ * Kernel timing.  When enabled, every kernel launch of a compute call is
+ * bracketed by hipEvents on the call's stream.  tlfea_get_profile
+ * synchronises those events and returns, per kernel id, the number of
+ * launches and their summed duration in milliseconds; reset clears them.
+ * Kernel ids: 0 forward tile, 1 adjoint tile, 2 tangent tile, 3 halo
+ * reduction, 4 whole batched graph replay.  ids: HOST int32[5] counts,
+ * ms: HOST double[5].
+ */
+tlfea_status tlfea_set_profiling(tlfea_mesh *mesh, int32_t enable);
+tlfea_status tlfea_get_profile(tlfea_mesh *mesh, int32_t *counts, double *ms);
+tlfea_status tlfea_reset_profile(tlfea_mesh *mesh);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLFEA_H */

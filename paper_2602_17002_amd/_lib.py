@@ -1,0 +1,87 @@
+"""ctypes declarations of the C ABI in include/tlfea.h (argument marshalling only).
+
+The shared library must have been built (``paper_2602_17002_amd/build.py``);
+there is no fallback path: a missing library raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtlfea.so")
+
+TLFEA_OK = 0
+STATUS_NAMES = {0: "TLFEA_OK", -1: "TLFEA_E_INVALID", -2: "TLFEA_E_SHAPE", -3: "TLFEA_E_REF_JACOBIAN",
+                -4: "TLFEA_E_NOMEM", -5: "TLFEA_E_DEVICE", -6: "TLFEA_E_UNSUPPORTED"}
+T10, H8 = 0, 1
+SVK, MR, NH = 0, 1, 2
+PLAIN, BATCHED, AUTOTUNE, KEEP_ORDER = 0, 1, 2, 4
+KERNEL_IDS = ("forward_tile", "adjoint_tile", "tangent_tile", "halo", "batched_graph")
+
+EXPORTS = ("tlfea_create_mesh", "tlfea_destroy_mesh", "tlfea_get_mesh_info", "tlfea_internal_force",
+           "tlfea_internal_force_vjp", "tlfea_tangent_jvp", "tlfea_last_error", "tlfea_set_profiling",
+           "tlfea_get_profile", "tlfea_reset_profile")
+
+
+class Block(C.Structure):
+    _fields_ = [("elem", C.c_int32), ("law", C.c_int32), ("n_elem", C.c_int64),
+                ("conn", C.POINTER(C.c_int32)), ("theta", C.c_double * 5),
+                ("damped", C.c_int32), ("tile_elems", C.c_int32)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_elem", C.c_int64), ("n_qp", C.c_int64),
+                ("n_tiles", C.c_int64), ("n_halo_nodes", C.c_int64), ("n_partials", C.c_int64),
+                ("n_blocks", C.c_int32), ("flags", C.c_int32),
+                ("tile_elems_t10", C.c_int32), ("tile_elems_h8", C.c_int32),
+                ("device_bytes", C.c_int64)]
+
+
+class TlfeaError(RuntimeError):
+    def __init__(self, status, what, msg):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+_lib = None
+
+
+def lib():
+    """Load libtlfea.so (raises ImportError if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2602_17002_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, dp = C.c_void_p, C.c_void_p
+    L.tlfea_create_mesh.argtypes = [C.c_int64, C.POINTER(C.c_double), C.c_int32, C.POINTER(Block), C.c_int32,
+                                    C.POINTER(vp)]
+    L.tlfea_create_mesh.restype = C.c_int
+    L.tlfea_destroy_mesh.argtypes = [vp]
+    L.tlfea_destroy_mesh.restype = None
+    L.tlfea_get_mesh_info.argtypes = [vp, C.POINTER(MeshInfo)]
+    L.tlfea_get_mesh_info.restype = C.c_int
+    L.tlfea_internal_force.argtypes = [vp, dp, dp, dp, dp, vp]
+    L.tlfea_internal_force.restype = C.c_int
+    L.tlfea_internal_force_vjp.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
+    L.tlfea_internal_force_vjp.restype = C.c_int
+    L.tlfea_tangent_jvp.argtypes = [vp, dp, dp, dp, dp, dp, dp, vp]
+    L.tlfea_tangent_jvp.restype = C.c_int
+    L.tlfea_last_error.argtypes = []
+    L.tlfea_last_error.restype = C.c_char_p
+    L.tlfea_set_profiling.argtypes = [vp, C.c_int32]
+    L.tlfea_set_profiling.restype = C.c_int
+    L.tlfea_get_profile.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.tlfea_get_profile.restype = C.c_int
+    L.tlfea_reset_profile.argtypes = [vp]
+    L.tlfea_reset_profile.restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(status, what):
+    if status != TLFEA_OK:
+        msg = lib().tlfea_last_error().decode(errors="replace")
+        raise TlfeaError(status, what, msg)

@@ -1,0 +1,851 @@
+// Host side of the C ABI declared in include/tlfea.h: argument validation,
+// element reordering, tiling, device upload, launch sequencing, hipGraph
+// replay for batched meshes, kernel timing and tile-size autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "tlfea.h"
+#include "tlfea_elements.h"
+#include "tlfea_internal.h"
+
+namespace tlfea {
+#define TLFEA_DECL(e, o)                                                                                   \
+    hipError_t launch_tiles_e##e##_o##o(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, \
+                                        const DevMesh &m, const CallArgs &c, int tile0, int NL);
+TLFEA_DECL(0, 0)
+TLFEA_DECL(0, 1)
+TLFEA_DECL(0, 2)
+TLFEA_DECL(1, 0)
+TLFEA_DECL(1, 1)
+TLFEA_DECL(1, 2)
+#undef TLFEA_DECL
+hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1);
+
+static hipError_t launch_tiles(int elem, int law, int damped, int te, int op, int n_tiles, size_t lds, hipStream_t s,
+                               const DevMesh &m, const CallArgs &c, int tile0, int NL)
+{
+    typedef hipError_t (*fn_t)(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int);
+    static const fn_t table[2][3] = {{launch_tiles_e0_o0, launch_tiles_e0_o1, launch_tiles_e0_o2},
+                                     {launch_tiles_e1_o0, launch_tiles_e1_o1, launch_tiles_e1_o2}};
+    if (elem < 0 || elem > 1 || op < 0 || op > 2) return hipErrorInvalidValue;
+    return table[elem][op](law, damped, te, n_tiles, lds, s, m, c, tile0, NL);
+}
+}  // namespace tlfea
+
+using namespace tlfea;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+static tlfea_status fail(tlfea_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                                      \
+    do {                                                                                                   \
+        hipError_t e_ = (expr);                                                                            \
+        if (e_ != hipSuccess)                                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? TLFEA_E_NOMEM : TLFEA_E_DEVICE, "%s: %s", #expr,      \
+                        hipGetErrorString(e_));                                                            \
+    } while (0)
+
+extern "C" const char *tlfea_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ element data (host)
+
+static int nen_of(int elem) { return elem == kT10 ? ElemDef<kT10>::nen : ElemDef<kH8>::nen; }
+static int nq_of(int elem) { return elem == kT10 ? ElemDef<kT10>::nq : ElemDef<kH8>::nq; }
+static int ncorner_of(int elem) { return elem == kT10 ? ElemDef<kT10>::n_corner : ElemDef<kH8>::n_corner; }
+static double grad_of(int elem, int q, int a, int k)
+{
+    return elem == kT10 ? ElemDef<kT10>::grad(q, a, k) : ElemDef<kH8>::grad(q, a, k);
+}
+
+// ------------------------------------------------------------------ mesh object
+
+struct ClassRange {
+    int elem, law, damped, te;
+    int tile_begin, tile_count;
+    int nl_cap;          // LDS row stride: max local nodes over the class's tiles
+};
+
+struct GraphEntry {
+    int op;
+    const void *key[9];
+    hipStream_t stream;
+    hipGraphExec_t exec;
+    uint64_t stamp;
+};
+
+struct tlfea_mesh {
+    int device = 0;
+    int flags = 0;
+    int64_t n_nodes = 0, n_elem = 0, n_qp = 0;
+    int n_blocks = 0;
+    std::vector<BlockDesc> blocks;
+    std::vector<ClassRange> classes;
+    int te_t10 = 0, te_h8 = 0;
+    DevMesh dm{};
+    std::vector<void *> allocations;
+    int64_t device_bytes = 0;
+    int64_t n_tiles = 0;
+    // profiling
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[5];
+    int32_t counts[5] = {0, 0, 0, 0, 0};
+    double ms[5] = {0, 0, 0, 0, 0};
+    // graph cache
+    std::vector<GraphEntry> graphs;
+    uint64_t stamp = 0;
+    bool any_damped = false;
+};
+
+static void free_mesh_memory(tlfea_mesh *m)
+{
+    for (void *p : m->allocations) hipFree(p);
+    m->allocations.clear();
+    for (auto &g : m->graphs) hipGraphExecDestroy(g.exec);
+    m->graphs.clear();
+    for (int k = 0; k < 5; ++k) {
+        for (auto &e : m->pending[k]) {
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+        m->pending[k].clear();
+    }
+}
+
+template <class T>
+static tlfea_status upload(tlfea_mesh *m, const std::vector<T> &h, T **d)
+{
+    *d = nullptr;
+    if (h.empty()) return TLFEA_OK;
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, h.size() * sizeof(T)));
+    m->allocations.push_back(p);
+    m->device_bytes += (int64_t)(h.size() * sizeof(T));
+    HIP_TRY(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    *d = static_cast<T *>(p);
+    return TLFEA_OK;
+}
+
+// ------------------------------------------------------------------ ordering
+
+static uint64_t spread21(uint64_t v)
+{
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+// Element order inside one block: Morton curve over element centroids so a
+// run of consecutive elements (a tile) is spatially compact.
+static void block_order(const tlfea_block &b, int64_t n_nodes, const double *X, bool keep, std::vector<int64_t> &ord)
+{
+    const int64_t ne = b.n_elem;
+    const int nen = nen_of(b.elem), nc = ncorner_of(b.elem);
+    ord.resize(ne);
+    for (int64_t e = 0; e < ne; ++e) ord[e] = e;
+    if (keep || ne < 2) return;
+    std::vector<double> cen(3 * ne);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t e = 0; e < ne; ++e)
+        for (int k = 0; k < 3; ++k) {
+            double s = 0;
+            for (int a = 0; a < nc; ++a) s += X[k * n_nodes + b.conn[e * nen + a]];
+            s /= nc;
+            cen[3 * e + k] = s;
+            lo[k] = std::min(lo[k], s);
+            hi[k] = std::max(hi[k], s);
+        }
+    double ext = 0;
+    for (int k = 0; k < 3; ++k) ext = std::max(ext, hi[k] - lo[k]);
+    if (!(ext > 0)) return;
+    std::vector<std::pair<uint64_t, int64_t>> key(ne);
+    for (int64_t e = 0; e < ne; ++e) {
+        uint64_t c = 0;
+        for (int k = 0; k < 3; ++k) {
+            double t = (cen[3 * e + k] - lo[k]) / ext;
+            uint64_t qv = (uint64_t)std::min(2097151.0, std::max(0.0, std::floor(t * 2097151.0)));
+            c |= spread21(qv) << k;
+        }
+        key[e] = {c, e};
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t e = 0; e < ne; ++e) ord[e] = key[e].second;
+}
+
+// ------------------------------------------------------------------ validation
+
+// J_p = det(U G(xi_q)) > 0 at every quadrature point (Sec. 6); also decides
+// whether J(xi) is the same at every point (affine parent map, Sec. 6).
+static tlfea_status check_element(int elem, const int32_t *c, int64_t n_nodes, const double *X, int64_t e, int b,
+                                  bool *affine)
+{
+    const int nen = nen_of(elem), nq = nq_of(elem);
+    double J0[9] = {0}, jmax = 0, dev = 0;
+    for (int q = 0; q < nq; ++q) {
+        double J[9] = {0};
+        for (int a = 0; a < nen; ++a)
+            for (int i = 0; i < 3; ++i) {
+                const double u = X[i * n_nodes + c[a]];
+                for (int k = 0; k < 3; ++k) J[3 * i + k] += u * grad_of(elem, q, a, k);
+            }
+        const double d = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                         J[2] * (J[3] * J[7] - J[4] * J[6]);
+        if (!(d > 0))
+            return fail(TLFEA_E_REF_JACOBIAN,
+                        "block %d element %lld: reference Jacobian det = %g <= 0 at quadrature point %d", b,
+                        (long long)e, d, q);
+        if (q == 0) {
+            std::memcpy(J0, J, sizeof J);
+            for (int k = 0; k < 9; ++k) jmax = std::max(jmax, std::fabs(J[k]));
+        } else {
+            for (int k = 0; k < 9; ++k) dev = std::max(dev, std::fabs(J[k] - J0[k]));
+        }
+    }
+    *affine = dev <= 1e-14 * jmax;
+    return TLFEA_OK;
+}
+
+// ------------------------------------------------------------------ tiling
+
+struct HostBuild {
+    std::vector<TileDesc> tiles;
+    std::vector<uint16_t> conn_local;
+    std::vector<int32_t> lnode_gid, lnode_dst, lnode_ptr;
+    std::vector<uint16_t> lnode_slot;
+    std::vector<int32_t> elem_uid;
+    std::vector<int32_t> halo_gid, halo_ptr, halo_slot;
+    int64_t n_part = 0;
+    std::vector<ClassRange> classes;
+};
+
+static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
+
+// Distinct nodes a tile may hold.  A compact tile of T10 needs about 2 per
+// element and one of H8 about 1.5; the cap also keeps the LDS staging of the
+// widest operation (tangent of a damped block: X, x, dx, v, dv) within the
+// per-workgroup LDS limit.
+static int nl_limit(int elem, int te, int damped, int64_t lds_limit)
+{
+    const int want = elem == kT10 ? (5 * te) / 2 : 2 * te;
+    const int arrays = 3 + 2 * (damped ? 1 : 0);
+    const int64_t fit = lds_limit / (arrays * 3 * (int64_t)sizeof(double));
+    return (int)std::min<int64_t>(want, fit) & ~1;
+}
+
+static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, const tlfea_block *blocks, int flags,
+                                const std::vector<int> &te_of_block, int64_t lds_limit, HostBuild &hb)
+{
+    // user element id offset per block
+    std::vector<int64_t> uid0(n_blocks + 1, 0);
+    for (int b = 0; b < n_blocks; ++b) uid0[b + 1] = uid0[b] + blocks[b].n_elem;
+    // classes: (elem, law, damped, te) in first-appearance order; tiles laid out class by class
+    struct Key {
+        int elem, law, damped, te;
+        bool operator==(const Key &o) const
+        {
+            return elem == o.elem && law == o.law && damped == o.damped && te == o.te;
+        }
+    };
+    std::vector<Key> keys;
+    std::vector<int> cls(n_blocks);
+    for (int b = 0; b < n_blocks; ++b) {
+        Key k{blocks[b].elem, blocks[b].law, blocks[b].damped ? 1 : 0, te_of_block[b]};
+        auto it = std::find(keys.begin(), keys.end(), k);
+        cls[b] = (int)(it - keys.begin());
+        if (it == keys.end()) keys.push_back(k);
+    }
+    std::vector<int32_t> mark(n_nodes, -1), local(n_nodes, -1);
+    std::vector<int32_t> tile_count(n_nodes, 0);
+    std::vector<int64_t> ord;
+    std::vector<int32_t> nodes;
+    int64_t elem_cursor = 0;
+    for (size_t k = 0; k < keys.size(); ++k) {
+        ClassRange cr{keys[k].elem, keys[k].law, keys[k].damped, keys[k].te, (int)hb.tiles.size(), 0, 0};
+        const int te = keys[k].te, nen = nen_of(keys[k].elem);
+        const int nlmax = nl_limit(keys[k].elem, te, keys[k].damped, lds_limit);
+        if ((int64_t)3 * nen * te * (int64_t)sizeof(double) > lds_limit || nlmax < nen)
+            return fail(TLFEA_E_UNSUPPORTED, "tile of %d elements does not fit %lld bytes of LDS", te,
+                        (long long)lds_limit);
+        for (int b = 0; b < n_blocks; ++b) {
+            if (cls[b] != (int)k) continue;
+            const tlfea_block &B = blocks[b];
+            block_order(B, n_nodes, X, (flags & TLFEA_KEEP_ORDER) != 0, ord);
+            int64_t pos = 0;
+            const int64_t ne = B.n_elem;
+            while (pos < ne) {
+                // greedy: take elements until te or the distinct-node limit
+                const int tile_id = (int)hb.tiles.size();
+                nodes.clear();
+                int64_t end = pos;
+                while (end < ne && end - pos < te) {
+                    const int32_t *c = B.conn + ord[end] * nen;
+                    int fresh = 0;
+                    for (int a = 0; a < nen; ++a)
+                        if (mark[c[a]] != tile_id) {
+                            bool dup = false;
+                            for (int a2 = 0; a2 < a; ++a2) dup |= c[a2] == c[a];
+                            fresh += dup ? 0 : 1;
+                        }
+                    if ((int)nodes.size() + fresh > nlmax && end > pos) break;
+                    for (int a = 0; a < nen; ++a)
+                        if (mark[c[a]] != tile_id) {
+                            mark[c[a]] = tile_id;
+                            nodes.push_back(c[a]);
+                        }
+                    ++end;
+                }
+                std::sort(nodes.begin(), nodes.end());
+                TileDesc t;
+                t.elem_begin = (int32_t)elem_cursor;
+                t.n_elem = (int32_t)(end - pos);
+                t.node_begin = (int32_t)hb.lnode_gid.size();
+                t.n_node = (int32_t)nodes.size();
+                t.ptr_begin = (int32_t)hb.lnode_ptr.size();
+                t.conn_begin = (int32_t)hb.conn_local.size();
+                t.block = b;
+                t.flags = 0;
+                for (size_t l = 0; l < nodes.size(); ++l) {
+                    local[nodes[l]] = (int32_t)l;
+                    hb.lnode_gid.push_back(nodes[l]);
+                    tile_count[nodes[l]] += 1;
+                }
+                // local connectivity [nen][te]
+                hb.conn_local.resize(hb.conn_local.size() + (size_t)nen * te, 0);
+                bool all_affine = true;
+                for (int64_t i = 0; i < end - pos; ++i) {
+                    const int64_t e = ord[pos + i];
+                    const int32_t *c = B.conn + e * nen;
+                    bool aff = false;
+                    tlfea_status st = check_element(B.elem, c, n_nodes, X, e, b, &aff);
+                    if (st != TLFEA_OK) return st;
+                    all_affine &= aff;
+                    for (int a = 0; a < nen; ++a) {
+                        const int l = local[c[a]];
+                        hb.conn_local[t.conn_begin + (size_t)a * te + i] = (uint16_t)l;
+                    }
+                    hb.elem_uid.push_back((int32_t)(uid0[b] + e));
+                }
+                if (all_affine) t.flags |= kTileAffine;
+                // per-node slot lists (CSR); visiting slots a * te + i in
+                // increasing order leaves every list sorted
+                {
+                    const size_t nn = nodes.size(), base = hb.lnode_slot.size();
+                    std::vector<int32_t> cnt(nn + 1, 0);
+                    const int64_t ne_t = end - pos;
+                    for (int a = 0; a < nen; ++a)
+                        for (int64_t i = 0; i < ne_t; ++i) cnt[hb.conn_local[t.conn_begin + (size_t)a * te + i] + 1]++;
+                    for (size_t l = 0; l < nn; ++l) cnt[l + 1] += cnt[l];
+                    for (size_t l = 0; l <= nn; ++l) hb.lnode_ptr.push_back((int32_t)(base + cnt[l]));
+                    hb.lnode_slot.resize(base + cnt[nn]);
+                    for (int a = 0; a < nen; ++a)
+                        for (int64_t i = 0; i < ne_t; ++i) {
+                            const int l = hb.conn_local[t.conn_begin + (size_t)a * te + i];
+                            hb.lnode_slot[base + cnt[l]++] = (uint16_t)(a * te + i);
+                        }
+                }
+                for (int32_t g : nodes) local[g] = -1;
+                cr.nl_cap = std::max(cr.nl_cap, (int)nodes.size());
+                hb.tiles.push_back(t);
+                elem_cursor += end - pos;
+                pos = end;
+            }
+        }
+        cr.tile_count = (int)hb.tiles.size() - cr.tile_begin;
+        cr.nl_cap = (cr.nl_cap + 1) & ~1;
+        if (cr.tile_count > 0) hb.classes.push_back(cr);
+    }
+    // owner of every local node: interior nodes are written by their tile,
+    // shared nodes get one partial slot per tile, summed in tile order
+    std::vector<std::vector<int32_t>> parts_of;   // indexed through halo index
+    std::vector<int32_t> halo_index(n_nodes, -1);
+    int32_t n_halo = 0;
+    for (int64_t g = 0; g < n_nodes; ++g)
+        if (tile_count[g] != 1) halo_index[g] = n_halo++;
+    parts_of.resize(n_halo);
+    hb.lnode_dst.resize(hb.lnode_gid.size());
+    int64_t n_part = 0;
+    for (size_t t = 0; t < hb.tiles.size(); ++t) {
+        const TileDesc &T = hb.tiles[t];
+        for (int l = 0; l < T.n_node; ++l) {
+            const int32_t g = hb.lnode_gid[T.node_begin + l];
+            if (tile_count[g] == 1) {
+                hb.lnode_dst[T.node_begin + l] = g;
+            } else {
+                if (n_part >= INT32_MAX) return fail(TLFEA_E_SHAPE, "too many shared-node partials");
+                parts_of[halo_index[g]].push_back((int32_t)n_part);
+                hb.lnode_dst[T.node_begin + l] = -1 - (int32_t)n_part;
+                ++n_part;
+            }
+        }
+    }
+    hb.n_part = n_part;
+    hb.halo_gid.reserve(n_halo);
+    hb.halo_ptr.reserve(n_halo + 1);
+    for (int64_t g = 0; g < n_nodes; ++g) {
+        const int32_t h = halo_index[g];
+        if (h < 0) continue;
+        hb.halo_gid.push_back((int32_t)g);
+        hb.halo_ptr.push_back((int32_t)hb.halo_slot.size());
+        for (int32_t p : parts_of[h]) hb.halo_slot.push_back(p);
+    }
+    hb.halo_ptr.push_back((int32_t)hb.halo_slot.size());
+    return TLFEA_OK;
+}
+
+// ------------------------------------------------------------------ create / destroy
+
+static tlfea_status validate_args(int64_t n_nodes, const double *X, int32_t n_blocks, const tlfea_block *blocks,
+                                  int32_t flags)
+{
+    if (n_nodes < 0 || n_nodes > INT32_MAX) return fail(TLFEA_E_SHAPE, "n_nodes = %lld out of range", (long long)n_nodes);
+    if (n_nodes > 0 && !X) return fail(TLFEA_E_INVALID, "X_ref is NULL");
+    if (n_blocks < 0 || (n_blocks > 0 && !blocks)) return fail(TLFEA_E_INVALID, "bad block list");
+    if (flags & ~(TLFEA_BATCHED | TLFEA_AUTOTUNE | TLFEA_KEEP_ORDER))
+        return fail(TLFEA_E_INVALID, "unknown flag bits 0x%x", flags);
+    for (int64_t i = 0; i < 3 * n_nodes; ++i)
+        if (!std::isfinite(X[i])) return fail(TLFEA_E_INVALID, "X_ref[%lld] is not finite", (long long)i);
+    int64_t total = 0;
+    for (int b = 0; b < n_blocks; ++b) {
+        const tlfea_block &B = blocks[b];
+        if (B.elem != TLFEA_T10 && B.elem != TLFEA_H8) return fail(TLFEA_E_INVALID, "block %d: unknown element %d", b, B.elem);
+        if (B.law != TLFEA_SVK && B.law != TLFEA_MR && B.law != TLFEA_NH)
+            return fail(TLFEA_E_INVALID, "block %d: unknown law %d", b, B.law);
+        if (B.n_elem < 0) return fail(TLFEA_E_SHAPE, "block %d: n_elem < 0", b);
+        if (B.n_elem > 0 && !B.conn) return fail(TLFEA_E_INVALID, "block %d: conn is NULL", b);
+        if (B.tile_elems != 0 && B.tile_elems != 64 && B.tile_elems != 128 && B.tile_elems != 256)
+            return fail(TLFEA_E_INVALID, "block %d: tile_elems must be 0, 64, 128 or 256", b);
+        for (int p = 0; p < 5; ++p)
+            if (!std::isfinite(B.theta[p])) return fail(TLFEA_E_INVALID, "block %d: theta[%d] not finite", b, p);
+        const int nen = nen_of(B.elem);
+        for (int64_t i = 0; i < B.n_elem * nen; ++i)
+            if (B.conn[i] < 0 || B.conn[i] >= n_nodes)
+                return fail(TLFEA_E_SHAPE, "block %d: conn[%lld] = %d outside [0, %lld)", b, (long long)i, B.conn[i],
+                            (long long)n_nodes);
+        for (int64_t e = 0; e < B.n_elem; ++e)
+            for (int a = 0; a < nen; ++a)
+                for (int a2 = 0; a2 < a; ++a2)
+                    if (B.conn[e * nen + a] == B.conn[e * nen + a2])
+                        return fail(TLFEA_E_SHAPE, "block %d element %lld repeats node %d", b, (long long)e,
+                                    B.conn[e * nen + a]);
+        total += B.n_elem;
+    }
+    if (total > INT32_MAX) return fail(TLFEA_E_SHAPE, "too many elements");
+    return TLFEA_OK;
+}
+
+static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_blocks, const tlfea_block *blocks,
+                                int32_t flags, const std::vector<int> &te_of_block, tlfea_mesh **out)
+{
+    // LDS per workgroup: the device's limit, at most 64 KiB so two
+    // workgroups of the largest tiles can share one compute unit
+    int64_t lds_limit = 65536;
+    {
+        int dev = 0, lim = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 0)
+            lds_limit = std::min<int64_t>(lds_limit, lim);
+        else
+            (void)hipGetLastError();
+    }
+    HostBuild hb;
+    tlfea_status st = build_tiles(n_nodes, X, n_blocks, blocks, flags, te_of_block, lds_limit, hb);
+    if (st != TLFEA_OK) return st;
+    tlfea_mesh *m = new (std::nothrow) tlfea_mesh();
+    if (!m) return fail(TLFEA_E_NOMEM, "host allocation failed");
+    hipGetDevice(&m->device);
+    m->flags = flags;
+    m->n_nodes = n_nodes;
+    m->n_blocks = n_blocks;
+    for (int b = 0; b < n_blocks; ++b) {
+        BlockDesc d;
+        for (int p = 0; p < 5; ++p) d.theta[p] = blocks[b].theta[p];
+        d.elem = blocks[b].elem;
+        d.law = blocks[b].law;
+        d.damped = blocks[b].damped ? 1 : 0;
+        d.pad = 0;
+        m->blocks.push_back(d);
+        m->n_elem += blocks[b].n_elem;
+        m->n_qp += blocks[b].n_elem * nq_of(blocks[b].elem);
+        m->any_damped |= blocks[b].damped != 0;
+        if (blocks[b].elem == kT10 && !m->te_t10) m->te_t10 = te_of_block[b];
+        if (blocks[b].elem == kH8 && !m->te_h8) m->te_h8 = te_of_block[b];
+    }
+    m->classes = hb.classes;
+    m->n_tiles = (int64_t)hb.tiles.size();
+    DevMesh &d = m->dm;
+    std::vector<double> Xv(X, X + 3 * n_nodes);
+    std::vector<double> part_dummy;
+#define UP(vec, ptr)                                                                                       \
+    do {                                                                                                   \
+        std::remove_const_t<std::remove_pointer_t<decltype(ptr)>> *p_ = nullptr;                           \
+        st = upload(m, vec, &p_);                                                                          \
+        if (st != TLFEA_OK) { free_mesh_memory(m); delete m; return st; }                                  \
+        ptr = p_;                                                                                          \
+    } while (0)
+    UP(hb.tiles, d.tiles);
+    UP(hb.conn_local, d.conn_local);
+    UP(hb.lnode_gid, d.lnode_gid);
+    UP(hb.lnode_dst, d.lnode_dst);
+    UP(hb.lnode_ptr, d.lnode_ptr);
+    UP(hb.lnode_slot, d.lnode_slot);
+    UP(hb.elem_uid, d.elem_uid);
+    UP(m->blocks, d.blocks);
+    UP(Xv, d.X);
+    UP(hb.halo_gid, d.halo_gid);
+    UP(hb.halo_ptr, d.halo_ptr);
+    UP(hb.halo_slot, d.halo_slot);
+#undef UP
+    d.n_nodes = n_nodes;
+    d.n_elem = m->n_elem;
+    d.n_part = hb.n_part;
+    d.n_halo = (int64_t)hb.halo_gid.size();
+    d.part = nullptr;
+    if (hb.n_part > 0) {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, sizeof(double) * 6 * (size_t)hb.n_part);
+        if (e != hipSuccess) {
+            free_mesh_memory(m);
+            delete m;
+            return fail(TLFEA_E_NOMEM, "hipMalloc of partial buffer: %s", hipGetErrorString(e));
+        }
+        m->allocations.push_back(p);
+        m->device_bytes += (int64_t)(sizeof(double) * 6 * hb.n_part);
+        d.part = static_cast<double *>(p);
+    }
+    *out = m;
+    return TLFEA_OK;
+}
+
+// ------------------------------------------------------------------ launching
+
+static size_t lds_bytes(const ClassRange &c, int op)
+{
+    int arrays = 2;   // X, x
+    if (op == kOpFwd) arrays += c.damped;                 // v
+    else if (op == kOpVjp) arrays += 1 + c.damped;        // w, v
+    else arrays += 1 + 2 * c.damped;                      // dx, v, dv
+    const size_t stage = (size_t)arrays * 3 * c.nl_cap * sizeof(double);
+    const size_t fe = (size_t)3 * nen_of(c.elem) * c.te * sizeof(double);
+    return std::max(stage, fe);
+}
+
+static tlfea_status enqueue(tlfea_mesh *m, int op, const CallArgs &c, hipStream_t s, bool timed)
+{
+    const int kid = op;   // kernel id: 0 fwd, 1 vjp, 2 jvp
+    for (const ClassRange &cr : m->classes) {
+        const size_t lds = lds_bytes(cr, op);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+            HIP_TRY(hipEventCreate(&e0));
+            HIP_TRY(hipEventCreate(&e1));
+            HIP_TRY(hipEventRecord(e0, s));
+        }
+        hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, s, m->dm, c,
+                                    cr.tile_begin, cr.nl_cap);
+        if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "tile kernel launch: %s", hipGetErrorString(e));
+        if (timed) {
+            HIP_TRY(hipEventRecord(e1, s));
+            m->pending[kid].push_back({e0, e1});
+        }
+    }
+    double *o1 = (op == kOpVjp) ? c.out1 : nullptr;
+    if (m->dm.n_halo > 0 && (c.out0 || o1)) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+            HIP_TRY(hipEventCreate(&e0));
+            HIP_TRY(hipEventCreate(&e1));
+            HIP_TRY(hipEventRecord(e0, s));
+        }
+        hipError_t e = launch_halo(s, m->dm, c.out0, o1);
+        if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "halo kernel launch: %s", hipGetErrorString(e));
+        if (timed) {
+            HIP_TRY(hipEventRecord(e1, s));
+            m->pending[3].push_back({e0, e1});
+        }
+    }
+    return TLFEA_OK;
+}
+
+static tlfea_status run(tlfea_mesh *m, int op, const CallArgs &c, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != m->device) return fail(TLFEA_E_INVALID, "current device %d differs from the mesh's device %d", dev, m->device);
+    // graphs cannot be captured on the null stream: launch directly there
+    if (!(m->flags & TLFEA_BATCHED) || s == nullptr) return enqueue(m, op, c, s, m->prof);
+    // batched: one hipGraph per (op, operand pointers, stream), replayed
+    const void *key[9] = {c.x, c.v, c.theta, c.w, c.dx, c.dv, c.out0, c.out1, c.gtheta};
+    GraphEntry *hit = nullptr;
+    for (auto &g : m->graphs)
+        if (g.op == op && g.stream == s && std::memcmp(g.key, key, sizeof key) == 0) hit = &g;
+    if (!hit) {
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        tlfea_status st = enqueue(m, op, c, s, false);
+        hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (st != TLFEA_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (ec != hipSuccess) return fail(TLFEA_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        GraphEntry ge;
+        ge.op = op;
+        std::memcpy(ge.key, key, sizeof key);
+        ge.stream = s;
+        ge.stamp = ++m->stamp;
+        hipError_t ei = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(TLFEA_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        if (m->graphs.size() >= 8) {
+            auto old = std::min_element(m->graphs.begin(), m->graphs.end(),
+                                        [](const GraphEntry &a, const GraphEntry &b) { return a.stamp < b.stamp; });
+            hipGraphExecDestroy(old->exec);
+            m->graphs.erase(old);
+        }
+        m->graphs.push_back(ge);
+        hit = &m->graphs.back();
+    }
+    hit->stamp = ++m->stamp;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (m->prof) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, s));
+    }
+    HIP_TRY(hipGraphLaunch(hit->exec, s));
+    if (m->prof) {
+        HIP_TRY(hipEventRecord(e1, s));
+        m->pending[4].push_back({e0, e1});
+    }
+    return TLFEA_OK;
+}
+
+static tlfea_status check_mesh(const tlfea_mesh *m)
+{
+    if (!m) return fail(TLFEA_E_INVALID, "mesh is NULL");
+    return TLFEA_OK;
+}
+
+extern "C" tlfea_status tlfea_internal_force(tlfea_mesh *m, const double *x, const double *v, const double *theta,
+                                             double *f, void *stream)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (m->n_nodes > 0 && (!x || !f)) return fail(TLFEA_E_INVALID, "x and f are required");
+    if (m->any_damped && m->n_elem > 0 && !v) return fail(TLFEA_E_INVALID, "v is required: a block is damped");
+    CallArgs c{};
+    c.x = x; c.v = v; c.theta = theta; c.out0 = f;
+    if (m->n_nodes == 0) return TLFEA_OK;
+    return run(m, kOpFwd, c, stream);
+}
+
+extern "C" tlfea_status tlfea_internal_force_vjp(tlfea_mesh *m, const double *x, const double *v, const double *theta,
+                                                 const double *w, double *gx, double *gv, double *gtheta, void *stream)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (m->n_nodes > 0 && (!x || !w)) return fail(TLFEA_E_INVALID, "x and w are required");
+    if (m->any_damped && m->n_elem > 0 && !v) return fail(TLFEA_E_INVALID, "v is required: a block is damped");
+    if (m->n_nodes == 0 || (!gx && !gv && !gtheta)) return TLFEA_OK;
+    CallArgs c{};
+    c.x = x; c.v = v; c.theta = theta; c.w = w; c.out0 = gx; c.out1 = gv; c.gtheta = gtheta;
+    return run(m, kOpVjp, c, stream);
+}
+
+extern "C" tlfea_status tlfea_tangent_jvp(tlfea_mesh *m, const double *x, const double *v, const double *theta,
+                                          const double *dx, const double *dv, double *df, void *stream)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (m->n_nodes > 0 && (!x || !df)) return fail(TLFEA_E_INVALID, "x and df are required");
+    if (m->any_damped && m->n_elem > 0 && !v) return fail(TLFEA_E_INVALID, "v is required: a block is damped");
+    if (m->n_nodes == 0) return TLFEA_OK;
+    CallArgs c{};
+    c.x = x; c.v = v; c.theta = theta; c.dx = dx; c.dv = m->any_damped ? dv : nullptr; c.out0 = df;
+    return run(m, kOpJvp, c, stream);
+}
+
+// ------------------------------------------------------------------ autotune
+
+// Time forward + adjoint per class for one candidate tile size.
+static tlfea_status time_classes(tlfea_mesh *m, std::vector<double> &t_cls)
+{
+    const size_t nb = sizeof(double) * 3 * (size_t)m->n_nodes;
+    double *x = nullptr, *v = nullptr, *w = nullptr, *o0 = nullptr, *o1 = nullptr;
+    HIP_TRY(hipMalloc(&x, nb));
+    HIP_TRY(hipMalloc(&v, nb));
+    HIP_TRY(hipMalloc(&w, nb));
+    HIP_TRY(hipMalloc(&o0, nb));
+    HIP_TRY(hipMalloc(&o1, nb));
+    HIP_TRY(hipMemcpy(x, m->dm.X, nb, hipMemcpyDeviceToDevice));
+    HIP_TRY(hipMemset(v, 0, nb));
+    HIP_TRY(hipMemset(w, 0, nb));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    t_cls.assign(m->classes.size(), 0.0);
+    for (size_t k = 0; k < m->classes.size(); ++k) {
+        const ClassRange &cr = m->classes[k];
+        for (int op = kOpFwd; op <= kOpVjp; ++op) {
+            CallArgs c{};
+            c.x = x; c.v = v; c.w = w; c.out0 = o0; c.out1 = o1;
+            const size_t lds = lds_bytes(cr, op);
+            float best = 1e30f;
+            for (int rep = 0; rep < 4; ++rep) {
+                HIP_TRY(hipEventRecord(e0, nullptr));
+                hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, nullptr, m->dm,
+                                            c, cr.tile_begin, cr.nl_cap);
+                if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "autotune launch: %s", hipGetErrorString(e));
+                HIP_TRY(hipEventRecord(e1, nullptr));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) best = std::min(best, ms);
+            }
+            t_cls[k] += best;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(x); hipFree(v); hipFree(w); hipFree(o0); hipFree(o1);
+    return TLFEA_OK;
+}
+
+extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int32_t n_blocks,
+                                          const tlfea_block *blocks, int32_t flags, tlfea_mesh **out)
+{
+    if (!out) return fail(TLFEA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    tlfea_status st = validate_args(n_nodes, X, n_blocks, blocks, flags);
+    if (st) return st;
+    std::vector<int> te(n_blocks);
+    for (int b = 0; b < n_blocks; ++b) te[b] = blocks[b].tile_elems ? blocks[b].tile_elems : default_te(blocks[b].elem);
+    if (!(flags & TLFEA_AUTOTUNE)) return create_with(n_nodes, X, n_blocks, blocks, flags, te, out);
+    // Autotune: per (element, law, damping) class, the tile size with the
+    // smallest forward + adjoint time over the class's own tiles; blocks that
+    // fix tile_elems keep it.
+    const int cand[3] = {64, 128, 256};
+    std::vector<double> best_t(n_blocks, 1e300);
+    std::vector<int> best_te = te;
+    for (int ci = 0; ci < 3; ++ci) {
+        std::vector<int> tc(n_blocks);
+        for (int b = 0; b < n_blocks; ++b) tc[b] = blocks[b].tile_elems ? blocks[b].tile_elems : cand[ci];
+        tlfea_mesh *m = nullptr;
+        st = create_with(n_nodes, X, n_blocks, blocks, flags & ~TLFEA_BATCHED, tc, &m);
+        if (st) return st;
+        std::vector<double> t;
+        st = time_classes(m, t);
+        if (st) {
+            tlfea_destroy_mesh(m);
+            return st;
+        }
+        for (int b = 0; b < n_blocks; ++b) {
+            if (blocks[b].tile_elems) continue;
+            for (size_t k = 0; k < m->classes.size(); ++k) {
+                const ClassRange &cr = m->classes[k];
+                if (cr.elem == blocks[b].elem && cr.law == blocks[b].law && cr.damped == (blocks[b].damped ? 1 : 0) &&
+                    t[k] < best_t[b]) {
+                    best_t[b] = t[k];
+                    best_te[b] = cand[ci];
+                }
+            }
+        }
+        tlfea_destroy_mesh(m);
+    }
+    return create_with(n_nodes, X, n_blocks, blocks, flags, best_te, out);
+}
+
+extern "C" void tlfea_destroy_mesh(tlfea_mesh *m)
+{
+    if (!m) return;
+    hipDeviceSynchronize();
+    free_mesh_memory(m);
+    delete m;
+}
+
+extern "C" tlfea_status tlfea_get_mesh_info(const tlfea_mesh *m, tlfea_mesh_info *info)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (!info) return fail(TLFEA_E_INVALID, "info is NULL");
+    info->n_nodes = m->n_nodes;
+    info->n_elem = m->n_elem;
+    info->n_qp = m->n_qp;
+    info->n_tiles = m->n_tiles;
+    info->n_halo_nodes = m->dm.n_halo;
+    info->n_partials = m->dm.n_part;
+    info->n_blocks = m->n_blocks;
+    info->flags = m->flags;
+    info->tile_elems_t10 = m->te_t10;
+    info->tile_elems_h8 = m->te_h8;
+    info->device_bytes = m->device_bytes;
+    return TLFEA_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+
+extern "C" tlfea_status tlfea_set_profiling(tlfea_mesh *m, int32_t enable)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    m->prof = enable != 0;
+    return TLFEA_OK;
+}
+
+extern "C" tlfea_status tlfea_get_profile(tlfea_mesh *m, int32_t *counts, double *ms)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    for (int k = 0; k < 5; ++k) {
+        for (auto &e : m->pending[k]) {
+            HIP_TRY(hipEventSynchronize(e.second));
+            float t = 0;
+            HIP_TRY(hipEventElapsedTime(&t, e.first, e.second));
+            m->ms[k] += t;
+            m->counts[k] += 1;
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+        m->pending[k].clear();
+        if (counts) counts[k] = m->counts[k];
+        if (ms) ms[k] = m->ms[k];
+    }
+    return TLFEA_OK;
+}
+
+extern "C" tlfea_status tlfea_reset_profile(tlfea_mesh *m)
+{
+    tlfea_status st = tlfea_get_profile(m, nullptr, nullptr);
+    if (st) return st;
+    for (int k = 0; k < 5; ++k) {
+        m->counts[k] = 0;
+        m->ms[k] = 0;
+    }
+    return TLFEA_OK;
+}

@@ -1,0 +1,55 @@
+// Device-side mesh layout shared by the host builder and the HIP kernels.
+#pragma once
+#include <stdint.h>
+
+namespace tlfea {
+
+// One tile = one workgroup: up to `te` elements of one block (one element
+// type, one law), their distinct nodes staged in LDS, and a tile-local CSR
+// that sums element contributions per node in a fixed order.
+struct TileDesc {
+    int32_t elem_begin;   // first internal element of the tile
+    int32_t n_elem;       // elements in the tile (<= te)
+    int32_t node_begin;   // first entry in lnode_gid / lnode_dst
+    int32_t n_node;       // distinct nodes of the tile
+    int32_t ptr_begin;    // first entry of this tile's lnode_ptr (n_node + 1 entries)
+    int32_t conn_begin;   // first entry of this tile's conn_local ([nen][te])
+    int32_t block;        // owning block
+    int32_t flags;        // bit 0: every element has an affine parent map
+};
+
+enum { kTileAffine = 1 };
+
+struct BlockDesc {
+    double theta[5];
+    int32_t elem, law, damped, pad;
+};
+
+// Pointers of the device mesh (all device memory owned by the mesh).
+struct DevMesh {
+    const TileDesc *tiles;
+    const uint16_t *conn_local;   // local node index per (tile, a, i)
+    const int32_t *lnode_gid;     // global node of each local node
+    const int32_t *lnode_dst;     // >= 0: global node written directly; < 0: -1 - partial slot
+    const int32_t *lnode_ptr;     // CSR offsets into lnode_slot
+    const uint16_t *lnode_slot;   // element-force slot = a * te + i
+    const int32_t *elem_uid;      // caller's element id of each internal element
+    const BlockDesc *blocks;
+    const double *X;              // [3][n_nodes]
+    const int32_t *halo_gid;      // nodes summed from partials (and orphans)
+    const int32_t *halo_ptr;      // [n_halo + 1]
+    const int32_t *halo_slot;     // partial slots, tile order
+    double *part;                 // [6][n_part] partial node sums
+    int64_t n_nodes, n_elem, n_part, n_halo;
+};
+
+// Per-call operands (device pointers; unused ones are null).
+struct CallArgs {
+    const double *x, *v, *theta, *w, *dx, *dv;
+    double *out0, *out1;   // f | gx, gv | df
+    double *gtheta;
+};
+
+enum { kOpFwd = 0, kOpVjp = 1, kOpJvp = 2 };
+
+}  // namespace tlfea

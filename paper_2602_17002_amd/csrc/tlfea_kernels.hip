@@ -1,0 +1,62 @@
+// One translation unit per (element type, operation): compiled with
+// -DTLFEA_ELEM=<0|1> -DTLFEA_OP=<0|1|2> so the instantiations build in
+// parallel.  The (T10, forward) unit also holds the shared-node kernel.
+#include "tlfea_device.h"
+
+#ifndef TLFEA_ELEM
+#error "TLFEA_ELEM must be defined"
+#endif
+#ifndef TLFEA_OP
+#error "TLFEA_OP must be defined"
+#endif
+
+#define TLFEA_CAT2(a, b, c) a##_e##b##_o##c
+#define TLFEA_CAT(a, b, c) TLFEA_CAT2(a, b, c)
+
+namespace tlfea {
+
+hipError_t TLFEA_CAT(launch_tiles, TLFEA_ELEM, TLFEA_OP)(int law, int damped, int te, int n_tiles, size_t lds,
+                                                          hipStream_t s, const DevMesh &m, const CallArgs &c,
+                                                          int tile0, int NL)
+{
+    return launch_class<TLFEA_OP, TLFEA_ELEM>(law, damped, te, n_tiles, lds, s, m, c, tile0, NL);
+}
+
+#if TLFEA_ELEM == 0 && TLFEA_OP == 0
+// Nodes shared between tiles (and nodes no element touches): sum the partial
+// slots in tile order.  One lane per node; up to two output fields.
+__global__ __launch_bounds__(256) void k_halo(DevMesh m, double *out0, double *out1)
+{
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= m.n_halo) return;
+    const int g = m.halo_gid[h];
+    const int p0 = m.halo_ptr[h], p1 = m.halo_ptr[h + 1];
+    double *outs[2] = {out0, out1};
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        double *out = outs[f];
+        if (!out) continue;
+        const double *part = m.part + (int64_t)(3 * f) * m.n_part;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int p = p0; p < p1; ++p) {
+            const int sl = m.halo_slot[p];
+            s0 += part[sl];
+            s1 += part[m.n_part + sl];
+            s2 += part[2 * m.n_part + sl];
+        }
+        out[g] = s0;
+        out[m.n_nodes + g] = s1;
+        out[2 * m.n_nodes + g] = s2;
+    }
+}
+
+hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1)
+{
+    if (m.n_halo <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((m.n_halo + 255) / 256));
+    k_halo<<<grid, 256, 0, s>>>(m, out0, out1);
+    return hipGetLastError();
+}
+#endif
+
+}  // namespace tlfea

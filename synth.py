@@ -1,6 +1,6 @@
 """Seeded synthetic inputs: box meshes, rigid motions, smooth deformations, materials.
 
-This module is shared by the CPU oracle's tests and by the GPU path's tests and
+A module of its own, shared by the CPU oracle's tests and by the GPU path's tests and
 benchmark.  It holds none of the method's arithmetic (no shape-function
 gradients, no kinematics, no stress): it only lays out reference nodes and
 connectivity, draws seeded states, and converts engineering material constants

@@ -1,0 +1,250 @@
+"""GPU parity: every output of the HIP path through the C ABI against the CPU
+oracle on the same seeded inputs, element by element (norm-wise relative
+error <= 1e-12), plus bitwise repeatability and the degenerate cases."""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from _util import TOL, rel, sub_blocks, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+LAWS = {
+    "SVK": (synth.SVK, np.array([5.769e6, 3.846e6, 0.0, 1.0e4, 3.0e3])),
+    "NH": (synth.NH, np.array([1.7e6, 0.0, 1.72667e7, 1.0e4, 3.0e3])),
+    "MR": (synth.MR, np.array([1.2e6, 0.45e6, 1.72667e7, 1.0e4, 3.0e3])),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def mesh_of(prob, flags=0, tile=None):
+    from paper_2602_17002_amd import Mesh
+    blocks = [copy.copy(b) for b in prob.blocks]
+    if tile:
+        for b in blocks:
+            b.tile_elems = tile
+    return Mesh(prob.X, blocks, flags=flags)
+
+
+def make_problem(elem, law, damped, n=(7, 5, 3), seed=0, curved=False, per_elem=False, cell=0.02):
+    rng = np.random.default_rng(seed)
+    lid, th = LAWS[law]
+    size = tuple(k * cell for k in n)
+    X, conn = (synth.box_t10 if elem == synth.T10 else synth.box_h8)(*n, size=size)
+    if curved:
+        if elem == synth.T10:
+            X = synth.curve_midside_t10(X, conn, 0.08, rng)
+        else:
+            X = X + rng.uniform(-0.08 * cell, 0.08 * cell, X.shape)
+    x = synth.sinusoidal_state(X, 0.05, rng)
+    x = x + rng.normal(0, 0.02 * cell, X.shape)
+    v = rng.normal(0, 0.5, X.shape) if damped else np.zeros_like(X)
+    th = th.copy()
+    if not damped:
+        th[3:] = 0
+    b = synth.Block(elem, lid, conn, th, damped=damped)
+    if per_elem:
+        b.theta_e = th[:, None] * rng.uniform(0.5, 2.0, (5, conn.shape[0]))
+    p = synth.Problem(f"{synth.ELEM_NAMES[elem]}-{law}-{'KV' if damped else 'el'}", X, x, v, [b], cell=cell)
+    p.w = rng.standard_normal(X.shape)
+    p.dx = rng.standard_normal(X.shape) * cell
+    p.dv = rng.standard_normal(X.shape)
+    return p
+
+
+CASES = [(e, l, d) for e in (synth.T10, synth.H8) for l in ("SVK", "NH", "MR") for d in (False, True)]
+
+
+def _id(c):
+    return f"{synth.ELEM_NAMES[c[0]]}-{c[1]}-{'KV' if c[2] else 'el'}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+@pytest.mark.parametrize("tile", [64, 256])
+def test_forward_matches_oracle(case, tile):
+    elem, law, damped = case
+    p = make_problem(elem, law, damped, curved=(tile == 64))
+    say("forward", p.name, "tile", tile, "elements", p.n_elem)
+    m = mesh_of(p, tile=tile)
+    f = to_host(m.internal_force(to_dev(p.x), to_dev(p.v) if damped else None))
+    ref = O.internal_force(p.X, p.blocks, p.x, p.v)
+    assert rel(f, ref) <= TOL, rel(f, ref)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_vjp_matches_oracle(case):
+    elem, law, damped = case
+    p = make_problem(elem, law, damped, per_elem=True, curved=True, seed=1)
+    say("vjp", p.name)
+    m = mesh_of(p, tile=128)
+    th = p.theta_all()
+    gx, gv, gt = m.vjp(to_dev(p.x), to_dev(p.v) if damped else None, to_dev(p.w), to_dev(th))
+    rx, rv, rt = O.vjp(p.X, p.blocks, p.x, p.v, p.w)
+    assert rel(to_host(gx), rx) <= TOL
+    if damped:
+        assert rel(to_host(gv), rv) <= TOL
+    else:
+        assert np.all(to_host(gv) == 0)
+    gt = to_host(gt)
+    for r in range(5):
+        if np.abs(rt[r]).max() == 0:
+            assert np.all(gt[r] == 0), r
+        else:
+            assert rel(gt[r], rt[r]) <= TOL, (r, rel(gt[r], rt[r]))
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+@pytest.mark.parametrize("which", ["dx+dv", "dx", "dv", "none"])
+def test_jvp_matches_oracle(case, which):
+    elem, law, damped = case
+    if not damped and which in ("dv", "dx+dv"):
+        pytest.skip("dv has no effect on an undamped body")
+    p = make_problem(elem, law, damped, per_elem=True, seed=2)
+    say("jvp", p.name, which)
+    m = mesh_of(p, tile=256)
+    dx = p.dx if "dx" in which else None
+    dv = p.dv if "dv" in which else None
+    th = p.theta_all()
+    df = to_host(m.jvp(to_dev(p.x), to_dev(p.v) if damped else None, None if dx is None else to_dev(dx),
+                       None if dv is None else to_dev(dv), to_dev(th)))
+    ref = O.jvp(p.X, p.blocks, p.x, p.v, dx, dv)
+    if which == "none":
+        assert np.all(df == 0)
+    else:
+        assert rel(df, ref) <= TOL, rel(df, ref)
+
+
+def test_c1_cantilever_all_outputs_and_repeatability():
+    p = synth.config_c1()
+    say("C1 cantilever", p.n_elem)
+    m = mesh_of(p)
+    x, v, w = to_dev(p.x), to_dev(p.v), to_dev(np.random.default_rng(3).standard_normal(p.X.shape))
+    f1 = to_host(m.internal_force(x, v))
+    f2 = to_host(m.internal_force(x, v))
+    assert np.array_equal(f1, f2)
+    assert rel(f1, O.internal_force(p.X, p.blocks, p.x, p.v)) <= TOL
+    gx, gv, gt = m.vjp(x, v, w)
+    rx, rv, rt = O.vjp(p.X, p.blocks, p.x, p.v, to_host(w))
+    assert rel(to_host(gx), rx) <= TOL and rel(to_host(gv), rv) <= TOL
+    gt = to_host(gt)
+    for r in (0, 1, 3):
+        assert rel(gt[r], rt[r]) <= TOL
+    assert np.all(gt[2] == 0) and rel(gt[4], rt[4]) <= TOL
+
+
+def test_keep_order_and_tile_sizes_agree():
+    p = make_problem(synth.T10, "NH", True, n=(9, 4, 3), seed=4)
+    say("orders", p.n_elem)
+    ref = O.internal_force(p.X, p.blocks, p.x, p.v)
+    from paper_2602_17002_amd import KEEP_ORDER
+    for flags in (0, KEEP_ORDER):
+        for tile in (64, 128, 256):
+            m = mesh_of(p, flags=flags, tile=tile)
+            f = to_host(m.internal_force(to_dev(p.x), to_dev(p.v)))
+            assert rel(f, ref) <= TOL, (flags, tile)
+
+
+def test_degenerate_meshes():
+    from paper_2602_17002_amd import Mesh
+    say("degenerate")
+    # one element, and nodes that no element touches (output must be 0 there)
+    X, conn = synth.box_t10(1, 1, 1, size=(0.1, 0.1, 0.1))
+    extra = np.random.default_rng(5).uniform(0, 1, (3, 7))
+    X2 = np.concatenate([X, extra], axis=1)
+    b = synth.Block(synth.T10, synth.NH, conn[:1].copy(), LAWS["NH"][1], damped=True)
+    rng = np.random.default_rng(6)
+    x = X2 + rng.normal(0, 1e-3, X2.shape); v = rng.normal(0, 1, X2.shape)
+    m = Mesh(X2, [b])
+    f = to_host(m.internal_force(to_dev(x), to_dev(v)))
+    ref = O.internal_force(X2, [b], x, v)
+    assert rel(f, ref) <= TOL
+    untouched = np.setdiff1d(np.arange(X2.shape[1]), conn[0])
+    assert np.all(f[:, untouched] == 0)
+    # a block with no elements next to a real one
+    e = synth.Block(synth.H8, synth.SVK, np.zeros((0, 8), np.int32), LAWS["SVK"][1], damped=False)
+    m = Mesh(X2, [e, b])
+    assert rel(to_host(m.internal_force(to_dev(x), to_dev(v))), ref) <= TOL
+    # no elements at all: f == 0
+    m = Mesh(X2, [e])
+    assert np.all(to_host(m.internal_force(to_dev(x), to_dev(v))) == 0)
+
+
+def test_multibody_batched_graph_equals_plain_and_oracle():
+    from paper_2602_17002_amd import BATCHED, Mesh
+    import torch
+    p = synth.config_multibody(12, 150, 3000, seed=7, directions=True)
+    say("multibody", len(p.blocks), p.n_elem)
+    ref = O.internal_force(p.X, p.blocks, p.x, p.v)
+    rx, rv, rt = O.vjp(p.X, p.blocks, p.x, p.v, p.w, want_gv=False)
+    rj = O.jvp(p.X, p.blocks, p.x, p.v, p.dx)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        x, w, dx = to_dev(p.x), to_dev(p.w), to_dev(p.dx)
+        plain = mesh_of(p)
+        batched = mesh_of(p, flags=BATCHED)
+        fp = plain.internal_force(x)
+        fb = torch.empty_like(x); gx = torch.empty_like(x); dfb = torch.empty_like(x)
+        gt = torch.empty((5, p.n_elem), dtype=torch.float64, device="cuda")
+        outs = []
+        for rep in range(3):   # first call captures, later calls replay the graph
+            for t in (fb, gx, dfb, gt):
+                t.fill_(float("nan"))
+            batched.internal_force(x, out=fb)
+            batched.vjp(x, None, w, want_v=False, out=(gx, None, gt))
+            batched.jvp(x, None, dx, out=dfb)
+            torch.cuda.synchronize()
+            outs.append((to_host(fb), to_host(gx), to_host(gt), to_host(dfb)))
+        torch.cuda.synchronize()
+    fp = to_host(fp)
+    assert rel(fp, ref) <= TOL
+    for fb, gx, gt, dfb in outs:
+        assert np.array_equal(fb, fp)
+        assert rel(gx, rx) <= TOL
+        assert rel(dfb, rj) <= TOL
+        for r in range(3):
+            if np.abs(rt[r]).max() > 0:
+                assert rel(gt[r], rt[r]) <= TOL
+    # per-body plain meshes give bitwise the same forces as the batched mesh
+    for bi in (0, 1, 5):
+        b = p.blocks[bi]
+        n0, n1 = p.body_nodes[bi]
+        bb = copy.copy(b); bb.conn = b.conn - n0
+        mb = Mesh(p.X[:, n0:n1], [bb])
+        fb1 = to_host(mb.internal_force(to_dev(p.x[:, n0:n1])))
+        assert np.array_equal(fb1, outs[0][0][:, n0:n1])
+
+
+def test_autograd_function():
+    import torch
+    from paper_2602_17002_amd import TLInternalForce
+    p = make_problem(synth.T10, "NH", True, n=(3, 3, 2), seed=8, per_elem=True)
+    say("autograd", p.n_elem)
+    m = mesh_of(p)
+    x = to_dev(p.x).requires_grad_(True)
+    v = to_dev(p.v).requires_grad_(True)
+    th = to_dev(p.theta_all()).requires_grad_(True)
+    w = to_dev(p.w)
+    f = TLInternalForce.apply(x, v, th, m)
+    (f * w).sum().backward()
+    rx, rv, rt = O.vjp(p.X, p.blocks, p.x, p.v, p.w)
+    assert rel(to_host(x.grad), rx) <= TOL
+    assert rel(to_host(v.grad), rv) <= TOL
+    assert rel(to_host(th.grad)[0], rt[0]) <= TOL
+    # forward mode
+    import torch.autograd.forward_ad as fwAD
+    dx, dv = to_dev(p.dx), to_dev(p.dv)
+    dth = to_dev(p.theta_all() * 0.1)
+    with fwAD.dual_level():
+        out = TLInternalForce.apply(fwAD.make_dual(x.detach(), dx), fwAD.make_dual(v.detach(), dv),
+                                    fwAD.make_dual(th.detach(), dth), m)
+        tangent = to_host(fwAD.unpack_dual(out).tangent)
+    ref = O.jvp(p.X, p.blocks, p.x, p.v, p.dx, p.dv)
+    b2 = copy.copy(p.blocks[0]); b2.theta_e = p.theta_all() * 0.1
+    ref = ref + O.internal_force(p.X, [b2], p.x, p.v)
+    assert rel(tangent, ref) <= TOL

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from paper_2602_17002_amd import synth
+import synth
 
 LAWS = {
     "SVK": (O.SVK, np.array([5.769e6, 3.846e6, 0.0, 1.0e4, 3.0e3])),
