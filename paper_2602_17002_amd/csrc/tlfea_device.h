@@ -104,7 +104,14 @@ __device__ __forceinline__ void qp_fence() { __asm__ __volatile__("" ::: "memory
 
 // G = sum_a s[:, ln[a]] (ds_a/dxi at point Q)^T, node data read from LDS
 // (row stride NL); zero gradient entries are removed at compile time.
-template <int ELEM, int Q, int NEN>
+//
+// CENTRED evaluates the same sum relative to the element's first node,
+// G = sum_{a>0} (s_a - s_0) (ds_a/dxi)^T, which is equal because the parent
+// gradients of a complete element sum to zero (partition of unity).  Used for
+// positions: a literal sum of coordinates of order 1 m against gradients of
+// order 1/h (h = 1 cm) cancels about two decimal digits that the differences
+// keep, so the result no longer depends on where the body sits in space.
+template <int ELEM, int Q, bool CENTRED, int NEN>
 __device__ __forceinline__ void grad_field(const double *__restrict__ s, int NL, const int (&ln)[NEN], m3 &G)
 {
     using E = ElemDef<ELEM>;
@@ -113,18 +120,23 @@ __device__ __forceinline__ void grad_field(const double *__restrict__ s, int NL,
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) G[i][k] = 0.0;
+    const double o0 = CENTRED ? s[ln[0]] : 0.0;
+    const double o1 = CENTRED ? s[NL + ln[0]] : 0.0;
+    const double o2 = CENTRED ? s[2 * NL + ln[0]] : 0.0;
     static_for<NEN>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        const double x0 = s[ln[a]], x1 = s[NL + ln[a]], x2 = s[2 * NL + ln[a]];
-        static_for<3>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            constexpr double g = E::grad(Q, a, k);
-            if constexpr (g != 0.0) {
-                G[0][k] += x0 * g;
-                G[1][k] += x1 * g;
-                G[2][k] += x2 * g;
-            }
-        });
+        if constexpr (!CENTRED || a > 0) {
+            const double x0 = s[ln[a]] - o0, x1 = s[NL + ln[a]] - o1, x2 = s[2 * NL + ln[a]] - o2;
+            static_for<3>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr double g = E::grad(Q, a, k);
+                if constexpr (g != 0.0) {
+                    G[0][k] += x0 * g;
+                    G[1][k] += x1 * g;
+                    G[2][k] += x2 * g;
+                }
+            });
+        }
     });
 }
 
@@ -153,7 +165,7 @@ __device__ __forceinline__ void ref_geometry(const double *__restrict__ sX, int 
                                              double &detJ)
 {
     m3 J, C;
-    grad_field<ELEM, Q>(sX, NL, ln, J);
+    grad_field<ELEM, Q, true>(sX, NL, ln, J);
     cofactor(J, C);
     detJ = det_from_cof(J, C);
     const double r = 1.0 / detJ;
@@ -379,10 +391,10 @@ __device__ __forceinline__ void fwd_element(const double *sX, const double *sx, 
         qp_fence();
         if constexpr (!AFFINE) ref_geometry<ELEM, q>(sX, NL, ln, Ji, detJ);
         m3 G, F, Fd, P;
-        grad_field<ELEM, q>(sx, NL, ln, G);
+        grad_field<ELEM, q, true>(sx, NL, ln, G);
         mm(G, Ji, F);                               // F = N H = (N dS/dxi) J^{-1}
         if constexpr (DAMPED) {
-            grad_field<ELEM, q>(sv, NL, ln, G);
+            grad_field<ELEM, q, false>(sv, NL, ln, G);
             mm(G, Ji, Fd);                          // Fdot = Ndot H
         }
         stress<LAW, DAMPED>(F, Fd, mt, P);
@@ -415,9 +427,9 @@ __device__ __forceinline__ void vjp_element(const double *sX, const double *sx, 
         qp_fence();
         if constexpr (!AFFINE) ref_geometry<ELEM, q>(sX, NL, ln, Ji, detJ);
         m3 G, F, Fd, Gw, Fb;
-        grad_field<ELEM, q>(sx, NL, ln, G);
+        grad_field<ELEM, q, true>(sx, NL, ln, G);
         mm(G, Ji, F);
-        grad_field<ELEM, q>(sw, NL, ln, G);
+        grad_field<ELEM, q, false>(sw, NL, ln, G);
         mm(G, Ji, Gw);
         const double c = E::weight(q) * detJ;
         MRState st;
@@ -445,7 +457,7 @@ __device__ __forceinline__ void vjp_element(const double *sX, const double *sx, 
             gt[2] += c * (st.J - 1.0) * st.J * GFiT;
         }
         if constexpr (DAMPED) {
-            grad_field<ELEM, q>(sv, NL, ln, G);
+            grad_field<ELEM, q, false>(sv, NL, ln, G);
             mm(G, Ji, Fd);
             m3 Ed, Sv, Sg, SvSg, T, A;
             sym_FtG(F, Fd, Ed);
@@ -497,10 +509,10 @@ __device__ __forceinline__ void jvp_element(const double *sX, const double *sx, 
         qp_fence();
         if constexpr (!AFFINE) ref_geometry<ELEM, q>(sX, NL, ln, Ji, detJ);
         m3 G, F, dF, dP;
-        grad_field<ELEM, q>(sx, NL, ln, G);
+        grad_field<ELEM, q, true>(sx, NL, ln, G);
         mm(G, Ji, F);
         {
-            grad_field<ELEM, q>(sdx, NL, ln, G);
+            grad_field<ELEM, q, false>(sdx, NL, ln, G);
             mm(G, Ji, dF);
             MRState st;
             if constexpr (LAW != 0) mr_state<LAW>(F, st);
@@ -508,7 +520,7 @@ __device__ __forceinline__ void jvp_element(const double *sX, const double *sx, 
         }
         if constexpr (DAMPED) {
             m3 Fd, Ed, Sv, A, B, T;
-            grad_field<ELEM, q>(sv, NL, ln, G);
+            grad_field<ELEM, q, false>(sv, NL, ln, G);
             mm(G, Ji, Fd);
             sym_FtG(F, Fd, Ed);
             visc_op(mt, Ed, Sv);
@@ -522,7 +534,7 @@ __device__ __forceinline__ void jvp_element(const double *sX, const double *sx, 
             }
             {
                 m3 dFd;
-                grad_field<ELEM, q>(sdv, NL, ln, G);
+                grad_field<ELEM, q, false>(sdv, NL, ln, G);
                 mm(G, Ji, dFd);
                 mTm(F, dFd, B);                   // F^T dFdot
 #pragma unroll

@@ -138,18 +138,25 @@ def random_rotation(rng):
 def sinusoidal_state(X, amp, rng, lengths=None):
     """x = R (X + u(X)) + t with a smooth sinusoidal u of peak gradient ``amp``.
 
-    u_i = amp * L_k / (2 pi) * sin(2 pi X_k / L_k + phi_i), k = (i+1) mod 3,
+    u_i = amp * sum_k c_ik * L_k / (2 pi) * sin(2 pi X_k / L_k + phi_ik), with
+    c_ik ~ U[-1, 1] scaled so that max_i sum_k |c_ik| = 1 (every entry of the
+    displacement gradient stays below ``amp``).  The gradient is a full
+    matrix, so the deformation has a volumetric part of first order in
+    ``amp`` (a field coupling each component to one other coordinate only
+    would be isochoric to third order and leave J - 1 ~ amp^3).
     R uniform on SO(3), t ~ N(0, 1 m).
     """
     if lengths is None:
         lengths = X.max(axis=1) - X.min(axis=1)
     lengths = np.maximum(np.asarray(lengths, dtype=np.float64), 1e-12)
-    phi = rng.uniform(0.0, 2 * np.pi, 3)
-    u = np.empty_like(X)
+    c = rng.uniform(-1.0, 1.0, (3, 3))
+    c /= np.abs(c).sum(axis=1).max()
+    phi = rng.uniform(0.0, 2 * np.pi, (3, 3))
+    u = np.zeros_like(X)
     for i in range(3):
-        k = (i + 1) % 3
-        L = lengths[k]
-        u[i] = amp * L / (2 * np.pi) * np.sin(2 * np.pi * X[k] / L + phi[i])
+        for k in range(3):
+            L = lengths[k]
+            u[i] += amp * c[i, k] * L / (2 * np.pi) * np.sin(2 * np.pi * X[k] / L + phi[i, k])
     R = random_rotation(rng)
     t = rng.standard_normal(3)
     return R @ (X + u) + t[:, None]

@@ -42,3 +42,62 @@ def sub_blocks(prob, nodes):
         cols.append(base + sel)
         base += b.n_elem
     return out, np.concatenate(cols)
+
+
+def centred(X, x, spans=None):
+    """Copies of X and x with each body moved so that its nodes' mean is at
+    the origin (spans: per-body (node_begin, node_end); None = one body).
+
+    The internal force and all its derivatives depend on X and x only
+    through differences of nodal values (the parent gradients of an element
+    sum to zero), so the oracle's exact result is unchanged.  Its FP64
+    rounding is not: a literal F = N H with coordinates of order 1 m on 1 cm
+    elements loses about two digits to cancellation, which on the
+    Neo-Hookean boxes amounts to a 1e-11 relative error, ten times the parity
+    bound.  The tests therefore evaluate the oracle on centred copies and
+    give the GPU the raw inputs; the GPU path is itself translation
+    invariant to rounding (it differences nodal positions per element)."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    x = np.array(x, dtype=np.float64, copy=True)
+    for n0, n1 in (spans or [(0, X.shape[1])]):
+        if n1 > n0:
+            X[:, n0:n1] -= X[:, n0:n1].mean(axis=1, keepdims=True)
+            x[:, n0:n1] -= x[:, n0:n1].mean(axis=1, keepdims=True)
+    return X, x
+
+
+def patch(prob, node, arrays=("x", "v", "w", "dx", "dv")):
+    """The elements incident to ``node`` as a small stand-alone problem with
+    local node numbering, centred on ``node`` (see ``centred``): everything the
+    oracle needs to evaluate assembled values at that node.  Returns
+    (X, blocks, {name: array}, local index of node, element columns)."""
+    sub, cols = sub_blocks(prob, [node])
+    used = np.unique(np.concatenate([b.conn.ravel() for b in sub if b.n_elem] + [np.array([node])]))
+    loc = np.full(prob.n_nodes, -1, dtype=np.int64)
+    loc[used] = np.arange(used.size)
+    out = []
+    for b in sub:
+        nb = copy.copy(b)
+        nb.conn = np.ascontiguousarray(loc[b.conn].astype(np.int32))
+        out.append(nb)
+    X = prob.X[:, used] - prob.X[:, [node]]
+    vals = {}
+    for name in arrays:
+        a = getattr(prob, name, None)
+        if a is not None:
+            vals[name] = np.ascontiguousarray(a[:, used])
+    if "x" in vals:
+        vals["x"] = vals["x"] - prob.x[:, [node]]
+    return np.ascontiguousarray(X), out, vals, int(loc[node]), cols
+
+
+def sample_nodes(prob, n_random, n_surface, seed):
+    """Random nodes plus random nodes on the boundary of the bounding box
+    (where the assembled forces are largest)."""
+    rng = np.random.default_rng(seed)
+    X = prob.X
+    lo, hi = X.min(axis=1, keepdims=True), X.max(axis=1, keepdims=True)
+    on_surface = np.nonzero(np.any(np.isclose(X, lo) | np.isclose(X, hi), axis=0))[0]
+    a = rng.choice(prob.n_nodes, n_random, replace=False)
+    b = rng.choice(on_surface, min(n_surface, on_surface.size), replace=False)
+    return np.unique(np.concatenate([a, b]))

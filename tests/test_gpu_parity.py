@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 import synth
-from _util import TOL, rel, sub_blocks, to_dev, to_host
+from _util import TOL, centred, rel, sub_blocks, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -17,6 +17,13 @@ LAWS = {
     "NH": (synth.NH, np.array([1.7e6, 0.0, 1.72667e7, 1.0e4, 3.0e3])),
     "MR": (synth.MR, np.array([1.2e6, 0.45e6, 1.72667e7, 1.0e4, 3.0e3])),
 }
+
+
+def oc(p):
+    """(X, blocks, x) for the oracle: per-body centred copies (f and its
+    derivatives depend only on nodal differences)."""
+    X, x = centred(p.X, p.x, p.body_nodes)
+    return X, p.blocks, x
 
 
 def say(*a):
@@ -73,7 +80,7 @@ def test_forward_matches_oracle(case, tile):
     say("forward", p.name, "tile", tile, "elements", p.n_elem)
     m = mesh_of(p, tile=tile)
     f = to_host(m.internal_force(to_dev(p.x), to_dev(p.v) if damped else None))
-    ref = O.internal_force(p.X, p.blocks, p.x, p.v)
+    ref = O.internal_force(*oc(p), p.v)
     assert rel(f, ref) <= TOL, rel(f, ref)
 
 
@@ -85,7 +92,7 @@ def test_vjp_matches_oracle(case):
     m = mesh_of(p, tile=128)
     th = p.theta_all()
     gx, gv, gt = m.vjp(to_dev(p.x), to_dev(p.v) if damped else None, to_dev(p.w), to_dev(th))
-    rx, rv, rt = O.vjp(p.X, p.blocks, p.x, p.v, p.w)
+    rx, rv, rt = O.vjp(*oc(p), p.v, p.w)
     assert rel(to_host(gx), rx) <= TOL
     if damped:
         assert rel(to_host(gv), rv) <= TOL
@@ -113,7 +120,7 @@ def test_jvp_matches_oracle(case, which):
     th = p.theta_all()
     df = to_host(m.jvp(to_dev(p.x), to_dev(p.v) if damped else None, None if dx is None else to_dev(dx),
                        None if dv is None else to_dev(dv), to_dev(th)))
-    ref = O.jvp(p.X, p.blocks, p.x, p.v, dx, dv)
+    ref = O.jvp(*oc(p), p.v, dx, dv)
     if which == "none":
         assert np.all(df == 0)
     else:
@@ -128,9 +135,9 @@ def test_c1_cantilever_all_outputs_and_repeatability():
     f1 = to_host(m.internal_force(x, v))
     f2 = to_host(m.internal_force(x, v))
     assert np.array_equal(f1, f2)
-    assert rel(f1, O.internal_force(p.X, p.blocks, p.x, p.v)) <= TOL
+    assert rel(f1, O.internal_force(*oc(p), p.v)) <= TOL
     gx, gv, gt = m.vjp(x, v, w)
-    rx, rv, rt = O.vjp(p.X, p.blocks, p.x, p.v, to_host(w))
+    rx, rv, rt = O.vjp(*oc(p), p.v, to_host(w))
     assert rel(to_host(gx), rx) <= TOL and rel(to_host(gv), rv) <= TOL
     gt = to_host(gt)
     for r in (0, 1, 3):
@@ -141,7 +148,7 @@ def test_c1_cantilever_all_outputs_and_repeatability():
 def test_keep_order_and_tile_sizes_agree():
     p = make_problem(synth.T10, "NH", True, n=(9, 4, 3), seed=4)
     say("orders", p.n_elem)
-    ref = O.internal_force(p.X, p.blocks, p.x, p.v)
+    ref = O.internal_force(*oc(p), p.v)
     from paper_2602_17002_amd import KEEP_ORDER
     for flags in (0, KEEP_ORDER):
         for tile in (64, 128, 256):
@@ -162,7 +169,8 @@ def test_degenerate_meshes():
     x = X2 + rng.normal(0, 1e-3, X2.shape); v = rng.normal(0, 1, X2.shape)
     m = Mesh(X2, [b])
     f = to_host(m.internal_force(to_dev(x), to_dev(v)))
-    ref = O.internal_force(X2, [b], x, v)
+    Xc, xc = centred(X2, x)
+    ref = O.internal_force(Xc, [b], xc, v)
     assert rel(f, ref) <= TOL
     untouched = np.setdiff1d(np.arange(X2.shape[1]), conn[0])
     assert np.all(f[:, untouched] == 0)
@@ -180,9 +188,9 @@ def test_multibody_batched_graph_equals_plain_and_oracle():
     import torch
     p = synth.config_multibody(12, 150, 3000, seed=7, directions=True)
     say("multibody", len(p.blocks), p.n_elem)
-    ref = O.internal_force(p.X, p.blocks, p.x, p.v)
-    rx, rv, rt = O.vjp(p.X, p.blocks, p.x, p.v, p.w, want_gv=False)
-    rj = O.jvp(p.X, p.blocks, p.x, p.v, p.dx)
+    ref = O.internal_force(*oc(p), p.v)
+    rx, rv, rt = O.vjp(*oc(p), p.v, p.w, want_gv=False)
+    rj = O.jvp(*oc(p), p.v, p.dx)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         x, w, dx = to_dev(p.x), to_dev(p.w), to_dev(p.dx)
@@ -232,7 +240,7 @@ def test_autograd_function():
     w = to_dev(p.w)
     f = TLInternalForce.apply(x, v, th, m)
     (f * w).sum().backward()
-    rx, rv, rt = O.vjp(p.X, p.blocks, p.x, p.v, p.w)
+    rx, rv, rt = O.vjp(*oc(p), p.v, p.w)
     assert rel(to_host(x.grad), rx) <= TOL
     assert rel(to_host(v.grad), rv) <= TOL
     assert rel(to_host(th.grad)[0], rt[0]) <= TOL
@@ -244,7 +252,67 @@ def test_autograd_function():
         out = TLInternalForce.apply(fwAD.make_dual(x.detach(), dx), fwAD.make_dual(v.detach(), dv),
                                     fwAD.make_dual(th.detach(), dth), m)
         tangent = to_host(fwAD.unpack_dual(out).tangent)
-    ref = O.jvp(p.X, p.blocks, p.x, p.v, p.dx, p.dv)
+    ref = O.jvp(*oc(p), p.v, p.dx, p.dv)
     b2 = copy.copy(p.blocks[0]); b2.theta_e = p.theta_all() * 0.1
-    ref = ref + O.internal_force(p.X, [b2], p.x, p.v)
+    ref = ref + O.internal_force(oc(p)[0], [b2], oc(p)[2], p.v)
     assert rel(tangent, ref) <= TOL
+
+
+def _full_size(cfg):
+    return {"C2": synth.config_c2, "C4": synth.config_c4}[cfg]()
+
+
+@pytest.mark.parametrize("cfg", ["C2", "C4"])
+def test_full_size_sampled_against_oracle(cfg):
+    """The benchmark's mesh sizes and launch configuration (library default
+    tiling): forward, adjoint (gx, gv, gtheta) and tangent on the whole mesh,
+    checked at sampled nodes (random ones plus boundary ones) and at the
+    elements incident to them, each evaluated by the oracle on its own patch."""
+    import torch
+    from _util import patch, sample_nodes
+    p = _full_size(cfg)
+    blk = p.blocks[0]
+    damped = blk.damped
+    say(cfg, "elements", p.n_elem, "nodes", p.n_nodes)
+    m = mesh_of(p)
+    x, v, w = to_dev(p.x), to_dev(p.v), to_dev(p.w)
+    th = to_dev(p.theta_all())
+    dx = to_dev(p.dx if p.dx is not None else np.random.default_rng(12).standard_normal(p.X.shape) * p.cell)
+    f = to_host(m.internal_force(x, v if damped else None, th))
+    gx, gv, gt = m.vjp(x, v if damped else None, w, th)
+    gx, gv, gt = to_host(gx), to_host(gv), to_host(gt)
+    df = to_host(m.jvp(x, v if damped else None, dx, None, th))
+    torch.cuda.synchronize()
+    dxh = to_host(dx)
+    p.dx = dxh
+    nodes = sample_nodes(p, 48, 16, seed=13)
+    got = {k: [] for k in ("f", "gx", "gv", "df", "gt")}
+    ref = {k: [] for k in got}
+    for n in nodes:
+        Xl, bl, a, i, cols = patch(p, int(n))
+        vl = a["v"] if damped else None
+        rf = O.internal_force(Xl, bl, a["x"], vl)
+        rx, rv, rt = O.vjp(Xl, bl, a["x"], vl, a["w"])
+        rj = O.jvp(Xl, bl, a["x"], vl, a["dx"])
+        got["f"].append(f[:, n]); ref["f"].append(rf[:, i])
+        got["gx"].append(gx[:, n]); ref["gx"].append(rx[:, i])
+        got["gv"].append(gv[:, n]); ref["gv"].append(rv[:, i] if damped else np.zeros(3))
+        got["df"].append(df[:, n]); ref["df"].append(rj[:, i])
+        got["gt"].append(gt[:, cols].T); ref["gt"].append(rt.T)
+    for k in got:
+        a = np.concatenate([np.ravel(t) for t in got[k]]) if k != "gt" else np.concatenate(got[k])
+        b = np.concatenate([np.ravel(t) for t in ref[k]]) if k != "gt" else np.concatenate(ref[k])
+        if k == "gt":
+            for r in range(5):
+                if np.abs(b[:, r]).max() == 0:
+                    assert np.all(a[:, r] == 0), (k, r)
+                else:
+                    e = rel(a[:, r], b[:, r])
+                    say(cfg, "gtheta row", r, "rel", e)
+                    assert e <= TOL, (k, r, e)
+        elif np.abs(b).max() == 0:
+            assert np.all(a == 0), k
+        else:
+            e = rel(a, b)
+            say(cfg, k, "rel", e)
+            assert e <= TOL, (k, e)
