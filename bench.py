@@ -122,6 +122,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="elements per tile (0 = library default)")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a kernel of known "
+                         "traffic, used to scale the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -150,6 +153,15 @@ def main():
         f = torch.empty_like(x)
         gx = torch.empty_like(x)
         gv = torch.empty_like(x)
+
+        if args.copy_calib_mb:
+            n = args.copy_calib_mb * (1 << 20) // 8
+            src = torch.ones(n, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"[bench] calibration copy of {args.copy_calib_mb} MiB done")
+            del src, dst
 
         def step():
             mesh.internal_force(x, v, out=f)

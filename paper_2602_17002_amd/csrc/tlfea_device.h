@@ -35,6 +35,21 @@ __device__ __forceinline__ void static_for(Fn &&fn)
     }
 }
 
+// Run fn(integral_constant<q>) for q = 0..N-1 as a loop that is not unrolled:
+// each iteration executes exactly one compile-time instance, so the
+// scheduler cannot interleave (and keep live) the temporaries of several
+// quadrature points.
+template <int N, class Fn>
+__device__ __forceinline__ void point_loop(Fn &&fn)
+{
+#pragma nounroll
+    for (int q = 0; q < N; ++q) {
+        static_for<N>([&](auto qc) {
+            if (q == decltype(qc)::value) fn(qc);
+        });
+    }
+}
+
 typedef double m3[3][3];
 
 __device__ __forceinline__ void mm(const m3 &A, const m3 &B, m3 &R)   // R = A B
@@ -94,25 +109,24 @@ struct Mat {
     double p0, p1, p2, mu_v, lam_v;
 };
 
-// Compiler-only barrier placed at the start of every quadrature point: node
-// values are re-read from LDS per point instead of being kept live in
-// registers across the unrolled point loop (which would cost 2 VGPRs per
-// staged double and halve occupancy).
+// Compiler-only barrier placed before every gather of a staged field: node
+// values are re-read from LDS when needed instead of being loaded early and
+// kept live in registers across the unrolled point loop (2 VGPRs per staged
+// double, which would halve occupancy).
 __device__ __forceinline__ void qp_fence() { __asm__ __volatile__("" ::: "memory"); }
 
 // -------------------------------------------------------- per-point kinematics
 
-// G = sum_a s[:, ln[a]] (ds_a/dxi at point Q)^T, node data read from LDS
-// (row stride NL); zero gradient entries are removed at compile time.
-//
-// CENTRED evaluates the same sum relative to the element's first node,
-// G = sum_{a>0} (s_a - s_0) (ds_a/dxi)^T, which is equal because the parent
-// gradients of a complete element sum to zero (partition of unity).  Used for
-// positions: a literal sum of coordinates of order 1 m against gradients of
-// order 1/h (h = 1 cm) cancels about two decimal digits that the differences
-// keep, so the result no longer depends on where the body sits in space.
-template <int ELEM, int Q, bool CENTRED, int NEN>
-__device__ __forceinline__ void grad_field(const double *__restrict__ s, int NL, const int (&ln)[NEN], m3 &G)
+// Node records in LDS: every staged node of a tile holds REC consecutive
+// doubles, field f's component c at offset 3 f + c.  na[a] is the record
+// offset (in doubles) of the element's local node a, so every read below is
+// one LDS address per node plus compile-time offsets.
+
+// G = sum_a s_a (ds_a/dxi at point Q)^T for the field at s (a pointer into
+// the first record at that field's offset); zero gradient entries are
+// removed at compile time.
+template <int ELEM, int Q, int NEN>
+__device__ __forceinline__ void grad_field(const double *__restrict__ s, const int (&na)[NEN], m3 &G)
 {
     using E = ElemDef<ELEM>;
     qp_fence();
@@ -120,23 +134,18 @@ __device__ __forceinline__ void grad_field(const double *__restrict__ s, int NL,
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) G[i][k] = 0.0;
-    const double o0 = CENTRED ? s[ln[0]] : 0.0;
-    const double o1 = CENTRED ? s[NL + ln[0]] : 0.0;
-    const double o2 = CENTRED ? s[2 * NL + ln[0]] : 0.0;
     static_for<NEN>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        if constexpr (!CENTRED || a > 0) {
-            const double x0 = s[ln[a]] - o0, x1 = s[NL + ln[a]] - o1, x2 = s[2 * NL + ln[a]] - o2;
-            static_for<3>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                constexpr double g = E::grad(Q, a, k);
-                if constexpr (g != 0.0) {
-                    G[0][k] += x0 * g;
-                    G[1][k] += x1 * g;
-                    G[2][k] += x2 * g;
-                }
-            });
-        }
+        const double x0 = s[na[a]], x1 = s[na[a] + 1], x2 = s[na[a] + 2];
+        static_for<3>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr double g = E::grad(Q, a, k);
+            if constexpr (g != 0.0) {
+                G[0][k] += x0 * g;
+                G[1][k] += x1 * g;
+                G[2][k] += x2 * g;
+            }
+        });
     });
 }
 
@@ -159,20 +168,40 @@ __device__ __forceinline__ void scatter_grad(const m3 &Qm, double (&out)[NEN][3]
     });
 }
 
-// Reference geometry at point Q: J = U G (Sec. 6), det J and J^{-1}.
+// Reference geometry at point Q (Sec. 6): J = U dS/dxi, J_p = det J,
+// K = cof(J) = J_p J^{-T} and r = 1 / J_p.  Evaluated at every point from
+// all nodes: straight-sided elements have a constant J only up to the
+// rounding of their mid-edge coordinates, which the bulk response amplifies.
 template <int ELEM, int Q, int NEN>
-__device__ __forceinline__ void ref_geometry(const double *__restrict__ sX, int NL, const int (&ln)[NEN], m3 &Ji,
-                                             double &detJ)
+__device__ __forceinline__ void ref_geometry(const double *__restrict__ sX, const int (&na)[NEN], m3 &K,
+                                             double &detJ, double &r)
 {
-    m3 J, C;
-    grad_field<ELEM, Q, true>(sX, NL, ln, J);
-    cofactor(J, C);
-    detJ = det_from_cof(J, C);
-    const double r = 1.0 / detJ;
+    m3 J;
+    grad_field<ELEM, Q>(sX, na, J);
+    cofactor(J, K);
+    detJ = det_from_cof(J, K);
+    r = 1.0 / detJ;
+}
+
+// A = G J^{-1} = (G K^T) r: the gradient with respect to the reference
+// coordinates of a field whose parent gradient is G (F = N H, Sec. 2.1).
+__device__ __forceinline__ void to_reference(const m3 &G, const m3 &K, double r, m3 &A)
+{
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) Ji[i][j] = C[j][i] * r;
+        for (int j = 0; j < 3; ++j) A[i][j] = (G[i][0] * K[j][0] + G[i][1] * K[j][1] + G[i][2] * K[j][2]) * r;
+}
+
+// Qm = w_q P K = w_q J_p P J^{-T}, so that w_q J_p P h_a = Qm (ds_a/dxi).
+__device__ __forceinline__ void to_parent(const m3 &P, const m3 &K, double wq, m3 &Qm)
+{
+    m3 T;
+    mm(P, K, T);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Qm[i][j] = T[i][j] * wq;
 }
 
 // ----------------------------------------------------------- constitutive laws
@@ -377,34 +406,42 @@ __device__ __forceinline__ Mat load_mat(const BlockDesc &b, const double *__rest
     return m;
 }
 
+// Offsets (in doubles) of the staged fields inside one LDS node record.
+// X and x always; the adjoint adds w, the tangent dx; damped blocks add v
+// (and the tangent dv).
+template <int OP, bool DAMPED>
+struct Rec {
+    static constexpr bool has2 = OP != kOpFwd;              // w or dx
+    static constexpr bool hasdv = DAMPED && OP == kOpJvp;
+    static constexpr int oX = 0, ox = 3, o2 = 6;
+    static constexpr int ov = has2 ? 9 : 6;
+    static constexpr int odv = ov + 3;
+    static constexpr int nfield = record_fields_len(OP, DAMPED) / 3;   // staged fields
+    static constexpr int len = record_len(OP, DAMPED);                  // stride (odd)
+    static_assert(3 * nfield == 6 + (has2 ? 3 : 0) + (DAMPED ? 3 : 0) + (hasdv ? 3 : 0), "record layout");
+};
+
 // Forward: fe[a] = sum_q w_q J_p P(F_q, Fdot_q) h_a   (Sec. 4.3 with Sec. 6)
-template <int ELEM, int LAW, bool DAMPED, bool AFFINE, int NEN>
-__device__ __forceinline__ void fwd_element(const double *sX, const double *sx, const double *sv, int NL,
-                                            const int (&ln)[NEN], const Mat &mt, double (&fe)[NEN][3])
+template <int ELEM, int LAW, bool DAMPED, int NEN>
+__device__ __forceinline__ void fwd_element(const double *sm, const int (&na)[NEN], const Mat &mt,
+                                            double (&fe)[NEN][3])
 {
     using E = ElemDef<ELEM>;
-    m3 Ji;
-    double detJ;
-    if constexpr (AFFINE) ref_geometry<ELEM, 0>(sX, NL, ln, Ji, detJ);
-    static_for<E::nq>([&](auto qc) {
+    using R = Rec<kOpFwd, DAMPED>;
+    point_loop<E::nq>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         qp_fence();
-        if constexpr (!AFFINE) ref_geometry<ELEM, q>(sX, NL, ln, Ji, detJ);
-        m3 G, F, Fd, P;
-        grad_field<ELEM, q, true>(sx, NL, ln, G);
-        mm(G, Ji, F);                               // F = N H = (N dS/dxi) J^{-1}
+        m3 K, G, F, Fd, P, Qm;
+        double detJ, r;
+        ref_geometry<ELEM, q>(sm + R::oX, na, K, detJ, r);
+        grad_field<ELEM, q>(sm + R::ox, na, G);
+        to_reference(G, K, r, F);                   // F = N H
         if constexpr (DAMPED) {
-            grad_field<ELEM, q, false>(sv, NL, ln, G);
-            mm(G, Ji, Fd);                          // Fdot = Ndot H
+            grad_field<ELEM, q>(sm + R::ov, na, G);
+            to_reference(G, K, r, Fd);              // Fdot = Ndot H
         }
         stress<LAW, DAMPED>(F, Fd, mt, P);
-        const double c = E::weight(q) * detJ;
-        m3 Qm;
-        mmT(P, Ji, Qm);                             // P J^{-T}: P h_a = (P J^{-T}) dS_a/dxi
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Qm[i][j] *= c;
+        to_parent(P, K, E::weight(q), Qm);
         scatter_grad<ELEM, q>(Qm, fe);
     });
 }
@@ -413,24 +450,22 @@ __device__ __forceinline__ void fwd_element(const double *sX, const double *sx, 
 //   gx_a += c_q Fbar_x h_a, Fbar_x = (dP_e/dF)[Gw] + Gw S_v + Fdot S_v[sym(F^T Gw)]
 //   gv_a += c_q Fbar_v h_a, Fbar_v = F S_v[sym(F^T Gw)]
 //   gtheta_p += c_q Gw : dP/dtheta_p   (P is linear in every parameter row)
-template <int ELEM, int LAW, bool DAMPED, bool AFFINE, int NEN>
-__device__ __forceinline__ void vjp_element(const double *sX, const double *sx, const double *sv, const double *sw,
-                                            int NL, const int (&ln)[NEN], const Mat &mt, double (&gx)[NEN][3],
-                                            double (&gv)[NEN][3], double (&gt)[5])
+template <int ELEM, int LAW, bool DAMPED, int NEN>
+__device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NEN], const Mat &mt,
+                                            double (&gx)[NEN][3], double (&gv)[NEN][3], double (&gt)[5])
 {
     using E = ElemDef<ELEM>;
-    m3 Ji;
-    double detJ;
-    if constexpr (AFFINE) ref_geometry<ELEM, 0>(sX, NL, ln, Ji, detJ);
-    static_for<E::nq>([&](auto qc) {
+    using R = Rec<kOpVjp, DAMPED>;
+    point_loop<E::nq>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         qp_fence();
-        if constexpr (!AFFINE) ref_geometry<ELEM, q>(sX, NL, ln, Ji, detJ);
-        m3 G, F, Fd, Gw, Fb;
-        grad_field<ELEM, q, true>(sx, NL, ln, G);
-        mm(G, Ji, F);
-        grad_field<ELEM, q, false>(sw, NL, ln, G);
-        mm(G, Ji, Gw);
+        m3 K, G, F, Gw, Fb;
+        double detJ, r;
+        ref_geometry<ELEM, q>(sm + R::oX, na, K, detJ, r);
+        grad_field<ELEM, q>(sm + R::ox, na, G);
+        to_reference(G, K, r, F);
+        grad_field<ELEM, q>(sm + R::o2, na, G);
+        to_reference(G, K, r, Gw);
         const double c = E::weight(q) * detJ;
         MRState st;
         if constexpr (LAW != 0) mr_state<LAW>(F, st);
@@ -457,16 +492,14 @@ __device__ __forceinline__ void vjp_element(const double *sX, const double *sx, 
             gt[2] += c * (st.J - 1.0) * st.J * GFiT;
         }
         if constexpr (DAMPED) {
-            grad_field<ELEM, q, false>(sv, NL, ln, G);
-            mm(G, Ji, Fd);
-            m3 Ed, Sv, Sg, SvSg, T, A;
+            m3 Fd, Ed, Sv, Sg, SvSg, T, A;
+            grad_field<ELEM, q>(sm + R::ov, na, G);
+            to_reference(G, K, r, Fd);
             sym_FtG(F, Fd, Ed);
             visc_op(mt, Ed, Sv);
             sym_FtG(F, Gw, Sg);
             visc_op(mt, Sg, SvSg);             // S_v[sym(F^T Gw)]
-            // parameter gradients of the viscous branch
-            double EdSg = ddot(Ed, Sg);
-            gt[3] += c * 2.0 * EdSg;
+            gt[3] += c * 2.0 * ddot(Ed, Sg);
             gt[4] += c * (Ed[0][0] + Ed[1][1] + Ed[2][2]) * GF;
             mm(Gw, Sv, T);
             mm(Fd, SvSg, A);
@@ -475,19 +508,11 @@ __device__ __forceinline__ void vjp_element(const double *sX, const double *sx, 
 #pragma unroll
                 for (int j = 0; j < 3; ++j) Fb[i][j] += T[i][j] + A[i][j];
             mm(F, SvSg, A);                        // Fbar_v
-            mmT(A, Ji, T);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) T[i][j] *= c;
+            to_parent(A, K, E::weight(q), T);
             scatter_grad<ELEM, q>(T, gv);
         }
         m3 Qm;
-        mmT(Fb, Ji, Qm);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Qm[i][j] *= c;
+        to_parent(Fb, K, E::weight(q), Qm);
         scatter_grad<ELEM, q>(Qm, gx);
     });
 }
@@ -495,47 +520,43 @@ __device__ __forceinline__ void vjp_element(const double *sX, const double *sx, 
 // Tangent: dF = sum_a dx_a h_a^T, dFdot = sum_a dv_a h_a^T,
 //   dP = (dP_e/dF)[dF] + dF S_v + F S_v[sym(dF^T Fdot + F^T dFdot)],
 //   df_a += c_q dP h_a.
-template <int ELEM, int LAW, bool DAMPED, bool AFFINE, int NEN>
-__device__ __forceinline__ void jvp_element(const double *sX, const double *sx, const double *sv, const double *sdx,
-                                            const double *sdv, int NL, const int (&ln)[NEN], const Mat &mt,
+template <int ELEM, int LAW, bool DAMPED, int NEN>
+__device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NEN], const Mat &mt,
                                             double (&df)[NEN][3])
 {
     using E = ElemDef<ELEM>;
-    m3 Ji;
-    double detJ;
-    if constexpr (AFFINE) ref_geometry<ELEM, 0>(sX, NL, ln, Ji, detJ);
-    static_for<E::nq>([&](auto qc) {
+    using R = Rec<kOpJvp, DAMPED>;
+    point_loop<E::nq>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         qp_fence();
-        if constexpr (!AFFINE) ref_geometry<ELEM, q>(sX, NL, ln, Ji, detJ);
-        m3 G, F, dF, dP;
-        grad_field<ELEM, q, true>(sx, NL, ln, G);
-        mm(G, Ji, F);
+        m3 K, G, F, dF, dP;
+        double detJ, r;
+        ref_geometry<ELEM, q>(sm + R::oX, na, K, detJ, r);
+        grad_field<ELEM, q>(sm + R::ox, na, G);
+        to_reference(G, K, r, F);
+        grad_field<ELEM, q>(sm + R::o2, na, G);
+        to_reference(G, K, r, dF);
         {
-            grad_field<ELEM, q, false>(sdx, NL, ln, G);
-            mm(G, Ji, dF);
             MRState st;
             if constexpr (LAW != 0) mr_state<LAW>(F, st);
             delastic<LAW>(F, mt, dF, st, dP);
         }
         if constexpr (DAMPED) {
             m3 Fd, Ed, Sv, A, B, T;
-            grad_field<ELEM, q, false>(sv, NL, ln, G);
-            mm(G, Ji, Fd);
+            grad_field<ELEM, q>(sm + R::ov, na, G);
+            to_reference(G, K, r, Fd);
             sym_FtG(F, Fd, Ed);
             visc_op(mt, Ed, Sv);
-            {
-                mm(dF, Sv, T);
+            mm(dF, Sv, T);
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) dP[i][j] += T[i][j];
-                mTm(dF, Fd, A);                   // dF^T Fdot
-            }
+                for (int j = 0; j < 3; ++j) dP[i][j] += T[i][j];
+            mTm(dF, Fd, A);                       // dF^T Fdot
             {
                 m3 dFd;
-                grad_field<ELEM, q, false>(sdv, NL, ln, G);
-                mm(G, Ji, dFd);
+                grad_field<ELEM, q>(sm + R::odv, na, G);
+                to_reference(G, K, r, dFd);
                 mTm(F, dFd, B);                   // F^T dFdot
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
@@ -553,169 +574,188 @@ __device__ __forceinline__ void jvp_element(const double *sX, const double *sx, 
 #pragma unroll
                 for (int j = 0; j < 3; ++j) dP[i][j] += T[i][j];
         }
-        const double c = E::weight(q) * detJ;
         m3 Qm;
-        mmT(dP, Ji, Qm);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Qm[i][j] *= c;
+        to_parent(dP, K, E::weight(q), Qm);
         scatter_grad<ELEM, q>(Qm, df);
     });
 }
 
 // ------------------------------------------------------------- tile plumbing
 
-// Stage the tile's nodes: dst[c * NL + l] = src[c * n + gid[l]].
-__device__ __forceinline__ void stage(double *__restrict__ dst, const double *__restrict__ src, int64_t n,
-                                      const int32_t *__restrict__ gid, int n_node, int NL, int tid, int nthreads)
+// The tiles of one class run as one grid.  Workgroups are handed to the
+// eight XCDs round-robin; consecutive tiles (spatial neighbours sharing
+// nodes) are mapped to the same XCD so that the node data they share is
+// fetched into one L2.  Returns -1 for the surplus workgroups (at most seven)
+// of the grid, which is rounded up to a multiple of eight.
+__device__ __forceinline__ int xcd_tile(int b, int n)
 {
-    for (int l = tid; l < n_node; l += nthreads) {
-        const int g = gid[l];
-        dst[l] = src[g];
-        dst[NL + l] = src[n + g];
-        dst[2 * NL + l] = src[2 * n + g];
+    const int per = (n + 7) >> 3;
+    const int t = (b & 7) * per + (b >> 3);
+    return t < n ? t : -1;
+}
+
+// Global source of field f of the LDS node record (record order X, x, then
+// w or dx, then v, then dv); null operands (dx or dv of the tangent) read as 0.
+template <int OP, bool DAMPED>
+__device__ __forceinline__ const double *field_src(int f, const DevMesh &m, const CallArgs &c)
+{
+    using R = Rec<OP, DAMPED>;
+    if (f == R::oX / 3) return m.X;
+    if (f == R::ox / 3) return c.x;
+    if (R::has2 && f == R::o2 / 3) return OP == kOpVjp ? c.w : c.dx;
+    if (DAMPED && f == R::ov / 3) return c.v;
+    return c.dv;
+}
+
+// Stage the tile's node records.  The host caps a tile at kStagePerThread x
+// (threads) nodes; every load of a thread is issued before its LDS stores.
+// Reference and current positions are staged relative to the tile's first
+// node: the kinematics only use differences of nodal positions (the parent
+// gradients of an element sum to zero), and coordinates of the size of a
+// tile instead of the size of the body keep the per-point gradient sums free
+// of cancellation.
+template <int OP, bool DAMPED>
+__device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMesh &m, const CallArgs &c,
+                                           const TileDesc &t, int tid, int nthr)
+{
+    using R = Rec<OP, DAMPED>;
+    constexpr int nf = R::nfield;
+    const int32_t *gid = m.lnode_gid + t.node_begin;
+    const int64_t n = m.n_nodes;
+    const int g0 = gid[0];
+    int g[kStagePerThread];
+#pragma unroll
+    for (int k = 0; k < kStagePerThread; ++k) {
+        const int l = tid + k * nthr;
+        g[k] = l < t.n_node ? gid[l] : -1;
     }
+    double v[kStagePerThread][3 * R::nfield];
+#pragma unroll
+    for (int f = 0; f < nf; ++f) {
+        const double *p = field_src<OP, DAMPED>(f, m, c);
+        const bool centre = f == R::oX / 3 || f == R::ox / 3;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const double o = centre ? p[cc * n + g0] : 0.0;
+#pragma unroll
+            for (int k = 0; k < kStagePerThread; ++k)
+                v[k][3 * f + cc] = (p && g[k] >= 0) ? p[cc * n + g[k]] - o : 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kStagePerThread; ++k)
+        if (g[k] >= 0) {
+            double *d = sm + (int64_t)(tid + k * nthr) * R::len;
+#pragma unroll
+            for (int j = 0; j < 3 * nf; ++j) d[j] = v[k][j];
+        }
 }
 
-// Write one element's nodal vectors to LDS at slot a * TE + i (row r at
-// r * NEN * TE), a layout in which consecutive lanes hit consecutive words.
-template <int NEN>
-__device__ __forceinline__ void put_slots(double *__restrict__ sf, const double (&v)[NEN][3], int i, int te)
+// Record offsets of the lane's element nodes (local connectivity [nen][te]).
+template <int NEN, int LEN>
+__device__ __forceinline__ void load_na(const DevMesh &m, const TileDesc &t, int i, int te, int (&na)[NEN])
 {
 #pragma unroll
-    for (int a = 0; a < NEN; ++a)
-#pragma unroll
-        for (int r = 0; r < 3; ++r) sf[r * NEN * te + a * te + i] = v[a][r];
+    for (int a = 0; a < NEN; ++a) na[a] = (int)m.conn_local[t.conn_begin + a * te + i] * LEN;
 }
 
-// Sum the slots of every local node in CSR order and write the node's value
-// either to the output vector (node owned by this tile only) or to its
-// partial slot (node shared between tiles).
-template <int NEN>
-__device__ __forceinline__ void reduce_nodes(const DevMesh &m, const TileDesc &t, const double *__restrict__ sf,
-                                             double *__restrict__ out, int field, int tid, int te)
+// Sum, for every local node, its element slots (CSR order) of one component
+// and write the value to the output (node owned by this tile only) or to the
+// node's partial slot in row `row` of the partial buffer (shared node).
+__device__ __forceinline__ void reduce_component(const DevMesh &m, const TileDesc &t,
+                                                 const double *__restrict__ slot, double *__restrict__ out,
+                                                 int row, int comp, int tid, int nthr)
 {
     const int32_t *ptr = m.lnode_ptr + t.ptr_begin;
     const int32_t *dst = m.lnode_dst + t.node_begin;
-    const int row = NEN * te;
-    for (int l = tid; l < t.n_node; l += te) {
+    for (int l = tid; l < t.n_node; l += nthr) {
         const int p0 = ptr[l], p1 = ptr[l + 1];
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int p = p0; p < p1; ++p) {
-            const int sl = m.lnode_slot[p];
-            s0 += sf[sl];
-            s1 += sf[row + sl];
-            s2 += sf[2 * row + sl];
-        }
+        double s = 0.0;
+        for (int p = p0; p < p1; ++p) s += slot[m.lnode_slot[p]];
         const int d = dst[l];
-        if (d >= 0) {
-            out[d] = s0;
-            out[m.n_nodes + d] = s1;
-            out[2 * m.n_nodes + d] = s2;
-        } else {
-            double *pp = m.part + (int64_t)(3 * field) * m.n_part + (-1 - d);
-            pp[0] = s0;
-            pp[m.n_part] = s1;
-            pp[2 * m.n_part] = s2;
-        }
+        if (d >= 0) out[comp * m.n_nodes + d] = s;
+        else m.part[(int64_t)row * m.n_part + (-1 - d)] = s;
     }
 }
 
-// Write zeros to every destination of the tile's nodes for output `field`
-// (an undamped tile's share of the velocity adjoint).
-__device__ __forceinline__ void zero_nodes(const DevMesh &m, const TileDesc &t, double *__restrict__ out, int field,
-                                           int tid, int te)
-{
-    const int32_t *dst = m.lnode_dst + t.node_begin;
-    for (int l = tid; l < t.n_node; l += te) {
-        const int d = dst[l];
-        if (d >= 0) {
-            out[d] = 0.0;
-            out[m.n_nodes + d] = 0.0;
-            out[2 * m.n_nodes + d] = 0.0;
-        } else {
-            double *pp = m.part + (int64_t)(3 * field) * m.n_part + (-1 - d);
-            pp[0] = 0.0;
-            pp[m.n_part] = 0.0;
-            pp[2 * m.n_part] = 0.0;
-        }
-    }
-}
-
+// Deterministic assembly of the element vectors of a tile, one component at
+// a time so that the LDS slots (a * te + i) need NEN x te doubles only; the
+// slots overwrite the node records, which are dead once every lane is done.
 template <int NEN>
-__device__ __forceinline__ void load_ln(const DevMesh &m, const TileDesc &t, int i, int te, int (&ln)[NEN])
+__device__ __forceinline__ void assemble(const DevMesh &m, const TileDesc &t, double *__restrict__ sm,
+                                         const double (&fe)[NEN][3], bool active, double *__restrict__ out,
+                                         int field, int tid, int te)
 {
 #pragma unroll
-    for (int a = 0; a < NEN; ++a) ln[a] = m.conn_local[t.conn_begin + a * te + i];
+    for (int r = 0; r < 3; ++r) {
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < NEN; ++a) sm[a * te + tid] = fe[a][r];
+        }
+        __syncthreads();
+        reduce_component(m, t, sm, out, 3 * field + r, r, tid, te);
+    }
+}
+
+// Zeros for every destination of the tile's nodes (an undamped tile's share
+// of the velocity adjoint).
+__device__ __forceinline__ void zero_nodes(const DevMesh &m, const TileDesc &t, double *__restrict__ out, int field,
+                                           int tid, int nthr)
+{
+    const int32_t *dst = m.lnode_dst + t.node_begin;
+    for (int l = tid; l < t.n_node; l += nthr) {
+        const int d = dst[l];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            if (d >= 0) out[r * m.n_nodes + d] = 0.0;
+            else m.part[(int64_t)(3 * field + r) * m.n_part + (-1 - d)] = 0.0;
+        }
+    }
 }
 
 // ----------------------------------------------------------------- kernels
 
-// Stage the tile's nodes of an optional operand; a null operand stages zeros.
-__device__ __forceinline__ void stage_or_zero(double *__restrict__ dst, const double *__restrict__ src, int64_t n,
-                                              const int32_t *__restrict__ gid, int n_node, int NL, int tid, int nthreads)
-{
-    if (src) {
-        stage(dst, src, n, gid, n_node, NL, tid, nthreads);
-    } else {
-        for (int l = tid; l < n_node; l += nthreads) dst[l] = dst[NL + l] = dst[2 * NL + l] = 0.0;
-    }
-}
-
 #define TLFEA_MAX_TE 256
 
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) void k_fwd(DevMesh m, CallArgs c, int tile0, int NL, int te)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LAW == 1 ? 2 : 3))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te)
 {
-    using E = ElemDef<ELEM>;
-    constexpr int NEN = E::nen;
+    constexpr int NEN = ElemDef<ELEM>::nen;
+    using R = Rec<kOpFwd, DAMPED>;
     extern __shared__ double smem[];
-    const TileDesc t = m.tiles[tile0 + blockIdx.x];
+    const int ti = xcd_tile(blockIdx.x, ntile);
+    if (ti < 0) return;
+    const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
-    double *sX = smem, *sx = smem + 3 * NL, *sv = smem + 6 * NL;
-    const int32_t *gid = m.lnode_gid + t.node_begin;
-    stage(sX, m.X, m.n_nodes, gid, t.n_node, NL, tid, te);
-    stage(sx, c.x, m.n_nodes, gid, t.n_node, NL, tid, te);
-    if constexpr (DAMPED) stage(sv, c.v, m.n_nodes, gid, t.n_node, NL, tid, te);
+    stage_tile<kOpFwd, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
-
     double fe[NEN][3];
 #pragma unroll
     for (int a = 0; a < NEN; ++a) fe[a][0] = fe[a][1] = fe[a][2] = 0.0;
     const bool active = tid < t.n_elem;
     if (active) {
-        int ln[NEN];
-        load_ln(m, t, tid, te, ln);
+        int na[NEN];
+        load_na<NEN, R::len>(m, t, tid, te, na);
         const int uid = m.elem_uid[t.elem_begin + tid];
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
-        if (t.flags & kTileAffine)
-            fwd_element<ELEM, LAW, DAMPED, true>(sX, sx, sv, NL, ln, mt, fe);
-        else
-            fwd_element<ELEM, LAW, DAMPED, false>(sX, sx, sv, NL, ln, mt, fe);
+        fwd_element<ELEM, LAW, DAMPED>(smem, na, mt, fe);
     }
-    __syncthreads();
-    if (active) put_slots<NEN>(smem, fe, tid, te);
-    __syncthreads();
-    reduce_nodes<NEN>(m, t, smem, c.out0, 0, tid, te);
+    assemble<NEN>(m, t, smem, fe, active, c.out0, 0, tid, te);
 }
 
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) void k_vjp(DevMesh m, CallArgs c, int tile0, int NL, int te)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te)
 {
-    using E = ElemDef<ELEM>;
-    constexpr int NEN = E::nen;
+    constexpr int NEN = ElemDef<ELEM>::nen;
+    using R = Rec<kOpVjp, DAMPED>;
     extern __shared__ double smem[];
-    const TileDesc t = m.tiles[tile0 + blockIdx.x];
+    const int ti = xcd_tile(blockIdx.x, ntile);
+    if (ti < 0) return;
+    const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
-    double *sX = smem, *sx = smem + 3 * NL, *sw = smem + 6 * NL, *sv = smem + 9 * NL;
-    const int32_t *gid = m.lnode_gid + t.node_begin;
-    stage(sX, m.X, m.n_nodes, gid, t.n_node, NL, tid, te);
-    stage(sx, c.x, m.n_nodes, gid, t.n_node, NL, tid, te);
-    stage(sw, c.w, m.n_nodes, gid, t.n_node, NL, tid, te);
-    if constexpr (DAMPED) stage(sv, c.v, m.n_nodes, gid, t.n_node, NL, tid, te);
+    stage_tile<kOpVjp, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
-
     double gx[NEN][3], gv[NEN][3], gt[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < NEN; ++a)
@@ -723,14 +763,11 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_vjp(DevMesh m, CallArgs c, int
         for (int r = 0; r < 3; ++r) gx[a][r] = gv[a][r] = 0.0;
     const bool active = tid < t.n_elem;
     if (active) {
-        int ln[NEN];
-        load_ln(m, t, tid, te, ln);
+        int na[NEN];
+        load_na<NEN, R::len>(m, t, tid, te, na);
         const int uid = m.elem_uid[t.elem_begin + tid];
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
-        if (t.flags & kTileAffine)
-            vjp_element<ELEM, LAW, DAMPED, true>(sX, sx, sv, sw, NL, ln, mt, gx, gv, gt);
-        else
-            vjp_element<ELEM, LAW, DAMPED, false>(sX, sx, sv, sw, NL, ln, mt, gx, gv, gt);
+        vjp_element<ELEM, LAW, DAMPED>(smem, na, mt, gx, gv, gt);
         if (c.gtheta) {
             // rows a law does not use (and the viscous rows when undamped) are 0
             c.gtheta[uid] = gt[0];
@@ -740,89 +777,65 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_vjp(DevMesh m, CallArgs c, int
             c.gtheta[4 * m.n_elem + uid] = DAMPED ? gt[4] : 0.0;
         }
     }
-    if (c.out0) {
-        __syncthreads();
-        if (active) put_slots<NEN>(smem, gx, tid, te);
-        __syncthreads();
-        reduce_nodes<NEN>(m, t, smem, c.out0, 0, tid, te);
-    }
+    if (c.out0) assemble<NEN>(m, t, smem, gx, active, c.out0, 0, tid, te);
     if (c.out1) {
-        if constexpr (DAMPED) {
-            __syncthreads();
-            if (active) put_slots<NEN>(smem, gv, tid, te);
-            __syncthreads();
-            reduce_nodes<NEN>(m, t, smem, c.out1, 1, tid, te);
-        } else {
-            zero_nodes(m, t, c.out1, 1, tid, te);
-        }
+        if constexpr (DAMPED) assemble<NEN>(m, t, smem, gv, active, c.out1, 1, tid, te);
+        else zero_nodes(m, t, c.out1, 1, tid, te);
     }
 }
 
 // The tangent stages dx (zeros when null) and, for damped blocks, dv (zeros
 // when null), so one instantiation serves every combination.
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int tile0, int NL, int te)
+__global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te)
 {
-    using E = ElemDef<ELEM>;
-    constexpr int NEN = E::nen;
+    constexpr int NEN = ElemDef<ELEM>::nen;
+    using R = Rec<kOpJvp, DAMPED>;
     extern __shared__ double smem[];
-    const TileDesc t = m.tiles[tile0 + blockIdx.x];
+    const int ti = xcd_tile(blockIdx.x, ntile);
+    if (ti < 0) return;
+    const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
-    double *sX = smem, *sx = smem + 3 * NL, *sdx = smem + 6 * NL, *sv = smem + 9 * NL, *sdv = smem + 12 * NL;
-    const int32_t *gid = m.lnode_gid + t.node_begin;
-    stage(sX, m.X, m.n_nodes, gid, t.n_node, NL, tid, te);
-    stage(sx, c.x, m.n_nodes, gid, t.n_node, NL, tid, te);
-    stage_or_zero(sdx, c.dx, m.n_nodes, gid, t.n_node, NL, tid, te);
-    if constexpr (DAMPED) {
-        stage(sv, c.v, m.n_nodes, gid, t.n_node, NL, tid, te);
-        stage_or_zero(sdv, c.dv, m.n_nodes, gid, t.n_node, NL, tid, te);
-    }
+    stage_tile<kOpJvp, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
-
     double df[NEN][3];
 #pragma unroll
     for (int a = 0; a < NEN; ++a) df[a][0] = df[a][1] = df[a][2] = 0.0;
     const bool active = tid < t.n_elem;
     if (active) {
-        int ln[NEN];
-        load_ln(m, t, tid, te, ln);
+        int na[NEN];
+        load_na<NEN, R::len>(m, t, tid, te, na);
         const int uid = m.elem_uid[t.elem_begin + tid];
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
-        if (t.flags & kTileAffine)
-            jvp_element<ELEM, LAW, DAMPED, true>(sX, sx, sv, sdx, sdv, NL, ln, mt, df);
-        else
-            jvp_element<ELEM, LAW, DAMPED, false>(sX, sx, sv, sdx, sdv, NL, ln, mt, df);
+        jvp_element<ELEM, LAW, DAMPED>(smem, na, mt, df);
     }
-    __syncthreads();
-    if (active) put_slots<NEN>(smem, df, tid, te);
-    __syncthreads();
-    reduce_nodes<NEN>(m, t, smem, c.out0, 0, tid, te);
+    assemble<NEN>(m, t, smem, df, active, c.out0, 0, tid, te);
 }
 
 template <int OP, int ELEM, int LAW, bool DAMPED>
 hipError_t launch_one(dim3 grid, int te, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c, int tile0,
-                      int NL)
+                      int ntile)
 {
-    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, NL, te);
-    else if constexpr (OP == kOpVjp) k_vjp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, NL, te);
-    else k_jvp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, NL, te);
+    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te);
+    else if constexpr (OP == kOpVjp) k_vjp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te);
+    else k_jvp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te);
     return hipGetLastError();
 }
 
 template <int OP, int ELEM>
 hipError_t launch_class(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m,
-                        const CallArgs &c, int tile0, int NL)
+                        const CallArgs &c, int tile0)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
-    const dim3 grid(n_tiles);
+    const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
     switch (law * 2 + (damped ? 1 : 0)) {
-    case 0: return launch_one<OP, ELEM, 0, false>(grid, te, lds, s, m, c, tile0, NL);
-    case 1: return launch_one<OP, ELEM, 0, true>(grid, te, lds, s, m, c, tile0, NL);
-    case 2: return launch_one<OP, ELEM, 1, false>(grid, te, lds, s, m, c, tile0, NL);
-    case 3: return launch_one<OP, ELEM, 1, true>(grid, te, lds, s, m, c, tile0, NL);
-    case 4: return launch_one<OP, ELEM, 2, false>(grid, te, lds, s, m, c, tile0, NL);
-    case 5: return launch_one<OP, ELEM, 2, true>(grid, te, lds, s, m, c, tile0, NL);
+    case 0: return launch_one<OP, ELEM, 0, false>(grid, te, lds, s, m, c, tile0, n_tiles);
+    case 1: return launch_one<OP, ELEM, 0, true>(grid, te, lds, s, m, c, tile0, n_tiles);
+    case 2: return launch_one<OP, ELEM, 1, false>(grid, te, lds, s, m, c, tile0, n_tiles);
+    case 3: return launch_one<OP, ELEM, 1, true>(grid, te, lds, s, m, c, tile0, n_tiles);
+    case 4: return launch_one<OP, ELEM, 2, false>(grid, te, lds, s, m, c, tile0, n_tiles);
+    case 5: return launch_one<OP, ELEM, 2, true>(grid, te, lds, s, m, c, tile0, n_tiles);
     default: return hipErrorInvalidValue;
     }
 }

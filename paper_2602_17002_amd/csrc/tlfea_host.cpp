@@ -21,7 +21,7 @@
 namespace tlfea {
 #define TLFEA_DECL(e, o)                                                                                   \
     hipError_t launch_tiles_e##e##_o##o(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, \
-                                        const DevMesh &m, const CallArgs &c, int tile0, int NL);
+                                        const DevMesh &m, const CallArgs &c, int tile0);
 TLFEA_DECL(0, 0)
 TLFEA_DECL(0, 1)
 TLFEA_DECL(0, 2)
@@ -32,13 +32,13 @@ TLFEA_DECL(1, 2)
 hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1);
 
 static hipError_t launch_tiles(int elem, int law, int damped, int te, int op, int n_tiles, size_t lds, hipStream_t s,
-                               const DevMesh &m, const CallArgs &c, int tile0, int NL)
+                               const DevMesh &m, const CallArgs &c, int tile0)
 {
-    typedef hipError_t (*fn_t)(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int);
+    typedef hipError_t (*fn_t)(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int);
     static const fn_t table[2][3] = {{launch_tiles_e0_o0, launch_tiles_e0_o1, launch_tiles_e0_o2},
                                      {launch_tiles_e1_o0, launch_tiles_e1_o1, launch_tiles_e1_o2}};
     if (elem < 0 || elem > 1 || op < 0 || op > 2) return hipErrorInvalidValue;
-    return table[elem][op](law, damped, te, n_tiles, lds, s, m, c, tile0, NL);
+    return table[elem][op](law, damped, te, n_tiles, lds, s, m, c, tile0);
 }
 }  // namespace tlfea
 
@@ -84,7 +84,7 @@ static double grad_of(int elem, int q, int a, int k)
 struct ClassRange {
     int elem, law, damped, te;
     int tile_begin, tile_count;
-    int nl_cap;          // LDS row stride: max local nodes over the class's tiles
+    int nl_cap;          // most distinct nodes of a tile of the class (LDS records to allocate)
 };
 
 struct GraphEntry {
@@ -199,18 +199,16 @@ static void block_order(const tlfea_block &b, int64_t n_nodes, const double *X, 
 
 // ------------------------------------------------------------------ validation
 
-// J_p = det(U G(xi_q)) > 0 at every quadrature point (Sec. 6); also decides
-// whether J(xi) is the same at every point (affine parent map, Sec. 6).
-static tlfea_status check_element(int elem, const int32_t *c, int64_t n_nodes, const double *X, int64_t e, int b,
-                                  bool *affine)
+// J_p = det(U G(xi_q)) > 0 at every quadrature point (Sec. 6).  Evaluated
+// with coordinates relative to the element's first node, as the kernels do.
+static tlfea_status check_element(int elem, const int32_t *c, int64_t n_nodes, const double *X, int64_t e, int b)
 {
     const int nen = nen_of(elem), nq = nq_of(elem);
-    double J0[9] = {0}, jmax = 0, dev = 0;
     for (int q = 0; q < nq; ++q) {
         double J[9] = {0};
-        for (int a = 0; a < nen; ++a)
+        for (int a = 1; a < nen; ++a)
             for (int i = 0; i < 3; ++i) {
-                const double u = X[i * n_nodes + c[a]];
+                const double u = X[i * n_nodes + c[a]] - X[i * n_nodes + c[0]];
                 for (int k = 0; k < 3; ++k) J[3 * i + k] += u * grad_of(elem, q, a, k);
             }
         const double d = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
@@ -219,14 +217,7 @@ static tlfea_status check_element(int elem, const int32_t *c, int64_t n_nodes, c
             return fail(TLFEA_E_REF_JACOBIAN,
                         "block %d element %lld: reference Jacobian det = %g <= 0 at quadrature point %d", b,
                         (long long)e, d, q);
-        if (q == 0) {
-            std::memcpy(J0, J, sizeof J);
-            for (int k = 0; k < 9; ++k) jmax = std::max(jmax, std::fabs(J[k]));
-        } else {
-            for (int k = 0; k < 9; ++k) dev = std::max(dev, std::fabs(J[k] - J0[k]));
-        }
     }
-    *affine = dev <= 1e-14 * jmax;
     return TLFEA_OK;
 }
 
@@ -238,27 +229,115 @@ struct HostBuild {
     std::vector<int32_t> lnode_gid, lnode_dst, lnode_ptr;
     std::vector<uint16_t> lnode_slot;
     std::vector<int32_t> elem_uid;
-    std::vector<int32_t> halo_gid, halo_ptr, halo_slot;
+    std::vector<int32_t> halo_gid, halo_ptr;
     int64_t n_part = 0;
     std::vector<ClassRange> classes;
 };
 
 static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
 
-// Distinct nodes a tile may hold.  A compact tile of T10 needs about 2 per
-// element and one of H8 about 1.5; the cap also keeps the LDS staging of the
-// widest operation (tangent of a damped block: X, x, dx, v, dv) within the
-// per-workgroup LDS limit.
-static int nl_limit(int elem, int te, int damped, int64_t lds_limit)
+// Distinct nodes a tile may hold: at most kStagePerThread per thread, and
+// few enough that the node records of the forward and adjoint fit 64 KiB of
+// LDS and those of the tangent (the widest record) fit the device's limit.
+static int nl_limit(int te, int damped, int64_t lds_dev)
 {
-    const int want = elem == kT10 ? (5 * te) / 2 : 2 * te;
-    const int arrays = 3 + 2 * (damped ? 1 : 0);
-    const int64_t fit = lds_limit / (arrays * 3 * (int64_t)sizeof(double));
-    return (int)std::min<int64_t>(want, fit) & ~1;
+    const int64_t fv = 65536 / (8 * (int64_t)record_len(kOpVjp, damped != 0));
+    const int64_t jv = lds_dev / (8 * (int64_t)record_len(kOpJvp, damped != 0));
+    return (int)std::min<int64_t>((int64_t)kStagePerThread * te, std::min(fv, jv));
+}
+
+// Cut the elements `ids` (one block, Morton order) into tiles of at most te
+// elements and nl_max distinct nodes.  A tile grows from the first element
+// not yet taken (in Morton order) by repeatedly adding the element that has
+// the most nodes already in the tile (fewest new nodes), the earliest
+// reached one among equals (breadth first), so tiles are compact and share
+// few nodes with their neighbours.  Appends the tiles' element lists
+// (positions in ids) to `out`.
+static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const std::vector<int64_t> &ids, int te, int nl_max,
+                       std::vector<std::vector<int64_t>> &out)
+{
+    const int nen = nen_of(B.elem);
+    const int64_t ne = (int64_t)ids.size();
+    // node -> elements (positions in ids)
+    std::vector<int64_t> nptr(n_nodes + 1, 0);
+    for (int64_t j = 0; j < ne; ++j)
+        for (int a = 0; a < nen; ++a) nptr[B.conn[ids[j] * nen + a] + 1]++;
+    for (int64_t g = 0; g < n_nodes; ++g) nptr[g + 1] += nptr[g];
+    std::vector<int64_t> nadj(nptr[n_nodes]);
+    {
+        std::vector<int64_t> fill(nptr.begin(), nptr.end() - 1);
+        for (int64_t j = 0; j < ne; ++j)
+            for (int a = 0; a < nen; ++a) nadj[fill[B.conn[ids[j] * nen + a]]++] = j;
+    }
+    std::vector<char> taken(ne, 0);
+    std::vector<int32_t> score(ne, 0), stamp(ne, -1), in_tile(n_nodes, -1);
+    std::vector<std::vector<int64_t>> bucket(nen + 1);   // candidates by score, read from head[]
+    std::vector<size_t> head(nen + 1, 0);
+    std::vector<int64_t> members;
+    int64_t cursor = 0;
+    int32_t tile = 0;
+    auto fresh_of = [&](int64_t j) {
+        int f = 0;
+        for (int a = 0; a < nen; ++a) f += in_tile[B.conn[ids[j] * nen + a]] == tile ? 0 : 1;
+        return f;
+    };
+    for (;; ++tile) {
+        while (cursor < ne && taken[cursor]) ++cursor;
+        if (cursor >= ne) break;
+        for (auto &bk : bucket) bk.clear();
+        std::fill(head.begin(), head.end(), 0);
+        members.clear();
+        int nodes = 0;
+        auto add = [&](int64_t j) {
+            taken[j] = 1;
+            members.push_back(j);
+            for (int a = 0; a < nen; ++a) {
+                const int32_t g = B.conn[ids[j] * nen + a];
+                if (in_tile[g] == tile) continue;
+                in_tile[g] = tile;
+                ++nodes;
+                for (int64_t p = nptr[g]; p < nptr[g + 1]; ++p) {
+                    const int64_t e2 = nadj[p];
+                    if (taken[e2]) continue;
+                    if (stamp[e2] != tile) {
+                        stamp[e2] = tile;
+                        score[e2] = 0;
+                    }
+                    score[e2] += 1;
+                    bucket[score[e2]].push_back(e2);
+                }
+            }
+        };
+        add(cursor);
+        while ((int)members.size() < te) {
+            int64_t best = -1;
+            for (int sc = nen; sc >= 1 && best < 0; --sc) {
+                auto &bk = bucket[sc];
+                while (head[sc] < bk.size()) {
+                    const int64_t j = bk[head[sc]];
+                    if (taken[j] || stamp[j] != tile || score[j] != sc) {
+                        ++head[sc];
+                        continue;
+                    }
+                    best = j;
+                    break;
+                }
+            }
+            if (best < 0) {   // no element touches the tile: continue with the next in Morton order
+                int64_t c2 = cursor;
+                while (c2 < ne && taken[c2]) ++c2;
+                if (c2 >= ne) break;
+                best = c2;
+            }
+            if (nodes + fresh_of(best) > nl_max) break;
+            add(best);
+        }
+        out.push_back(members);
+    }
 }
 
 static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, const tlfea_block *blocks, int flags,
-                                const std::vector<int> &te_of_block, int64_t lds_limit, HostBuild &hb)
+                                const std::vector<int> &te_of_block, int64_t lds_dev, HostBuild &hb)
 {
     // user element id offset per block
     std::vector<int64_t> uid0(n_blocks + 1, 0);
@@ -279,56 +358,76 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
         cls[b] = (int)(it - keys.begin());
         if (it == keys.end()) keys.push_back(k);
     }
-    std::vector<int32_t> mark(n_nodes, -1), local(n_nodes, -1);
+    for (int b = 0; b < n_blocks; ++b) {
+        const tlfea_block &B = blocks[b];
+        for (int64_t e = 0; e < B.n_elem; ++e) {
+            tlfea_status st = check_element(B.elem, B.conn + e * nen_of(B.elem), n_nodes, X, e, b);
+            if (st != TLFEA_OK) return st;
+        }
+    }
+    std::vector<int32_t> local(n_nodes, -1);
     std::vector<int32_t> tile_count(n_nodes, 0);
     std::vector<int64_t> ord;
     std::vector<int32_t> nodes;
+    std::vector<std::vector<int64_t>> groups;
     int64_t elem_cursor = 0;
     for (size_t k = 0; k < keys.size(); ++k) {
         ClassRange cr{keys[k].elem, keys[k].law, keys[k].damped, keys[k].te, (int)hb.tiles.size(), 0, 0};
         const int te = keys[k].te, nen = nen_of(keys[k].elem);
-        const int nlmax = nl_limit(keys[k].elem, te, keys[k].damped, lds_limit);
-        if ((int64_t)3 * nen * te * (int64_t)sizeof(double) > lds_limit || nlmax < nen)
-            return fail(TLFEA_E_UNSUPPORTED, "tile of %d elements does not fit %lld bytes of LDS", te,
-                        (long long)lds_limit);
+        const int nlmax = nl_limit(te, keys[k].damped, lds_dev);
+        if (nlmax < nen || (int64_t)nen * te * (int64_t)sizeof(double) > 65536)
+            return fail(TLFEA_E_UNSUPPORTED, "tile of %d elements does not fit the LDS of one workgroup", te);
         for (int b = 0; b < n_blocks; ++b) {
             if (cls[b] != (int)k) continue;
             const tlfea_block &B = blocks[b];
             block_order(B, n_nodes, X, (flags & TLFEA_KEEP_ORDER) != 0, ord);
-            int64_t pos = 0;
-            const int64_t ne = B.n_elem;
-            while (pos < ne) {
-                // greedy: take elements until te or the distinct-node limit
-                const int tile_id = (int)hb.tiles.size();
+            groups.clear();
+            if (flags & TLFEA_KEEP_ORDER) {
+                // consecutive runs of the caller's order, cut at te elements or nlmax nodes
+                int64_t pos = 0;
+                while (pos < B.n_elem) {
+                    std::vector<int64_t> g;
+                    nodes.clear();
+                    while (pos < B.n_elem && (int)g.size() < te) {
+                        const int32_t *c = B.conn + ord[pos] * nen;
+                        int fresh = 0;
+                        for (int a = 0; a < nen; ++a) fresh += local[c[a]] < 0 ? 1 : 0;
+                        if ((int)nodes.size() + fresh > nlmax && !g.empty()) break;
+                        for (int a = 0; a < nen; ++a)
+                            if (local[c[a]] < 0) {
+                                local[c[a]] = 1;
+                                nodes.push_back(c[a]);
+                            }
+                        g.push_back(pos++);
+                    }
+                    for (int32_t gg : nodes) local[gg] = -1;
+                    groups.push_back(std::move(g));
+                }
+            } else {
+                grow_tiles(B, n_nodes, ord, te, nlmax, groups);
+            }
+            for (const auto &grp : groups) {
                 nodes.clear();
-                int64_t end = pos;
-                while (end < ne && end - pos < te) {
-                    const int32_t *c = B.conn + ord[end] * nen;
-                    int fresh = 0;
+                for (int64_t pos : grp) {
+                    const int32_t *c = B.conn + ord[pos] * nen;
                     for (int a = 0; a < nen; ++a)
-                        if (mark[c[a]] != tile_id) {
-                            bool dup = false;
-                            for (int a2 = 0; a2 < a; ++a2) dup |= c[a2] == c[a];
-                            fresh += dup ? 0 : 1;
-                        }
-                    if ((int)nodes.size() + fresh > nlmax && end > pos) break;
-                    for (int a = 0; a < nen; ++a)
-                        if (mark[c[a]] != tile_id) {
-                            mark[c[a]] = tile_id;
+                        if (local[c[a]] < 0) {
+                            local[c[a]] = 1;
                             nodes.push_back(c[a]);
                         }
-                    ++end;
                 }
                 std::sort(nodes.begin(), nodes.end());
                 TileDesc t;
                 t.elem_begin = (int32_t)elem_cursor;
-                t.n_elem = (int32_t)(end - pos);
+                t.n_elem = (int32_t)grp.size();
                 t.node_begin = (int32_t)hb.lnode_gid.size();
                 t.n_node = (int32_t)nodes.size();
                 t.ptr_begin = (int32_t)hb.lnode_ptr.size();
                 t.conn_begin = (int32_t)hb.conn_local.size();
                 t.block = b;
-                t.flags = 0;
+                t.pad = 0;
+                if (t.n_node > nlmax || t.n_node > kStagePerThread * te)
+                    return fail(TLFEA_E_UNSUPPORTED, "tile with %d nodes exceeds the limit %d", t.n_node, nlmax);
                 for (size_t l = 0; l < nodes.size(); ++l) {
                     local[nodes[l]] = (int32_t)l;
                     hb.lnode_gid.push_back(nodes[l]);
@@ -336,27 +435,19 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                 }
                 // local connectivity [nen][te]
                 hb.conn_local.resize(hb.conn_local.size() + (size_t)nen * te, 0);
-                bool all_affine = true;
-                for (int64_t i = 0; i < end - pos; ++i) {
-                    const int64_t e = ord[pos + i];
+                for (size_t i = 0; i < grp.size(); ++i) {
+                    const int64_t e = ord[grp[i]];
                     const int32_t *c = B.conn + e * nen;
-                    bool aff = false;
-                    tlfea_status st = check_element(B.elem, c, n_nodes, X, e, b, &aff);
-                    if (st != TLFEA_OK) return st;
-                    all_affine &= aff;
-                    for (int a = 0; a < nen; ++a) {
-                        const int l = local[c[a]];
-                        hb.conn_local[t.conn_begin + (size_t)a * te + i] = (uint16_t)l;
-                    }
+                    for (int a = 0; a < nen; ++a)
+                        hb.conn_local[t.conn_begin + (size_t)a * te + i] = (uint16_t)local[c[a]];
                     hb.elem_uid.push_back((int32_t)(uid0[b] + e));
                 }
-                if (all_affine) t.flags |= kTileAffine;
                 // per-node slot lists (CSR); visiting slots a * te + i in
                 // increasing order leaves every list sorted
                 {
                     const size_t nn = nodes.size(), base = hb.lnode_slot.size();
                     std::vector<int32_t> cnt(nn + 1, 0);
-                    const int64_t ne_t = end - pos;
+                    const int64_t ne_t = (int64_t)grp.size();
                     for (int a = 0; a < nen; ++a)
                         for (int64_t i = 0; i < ne_t; ++i) cnt[hb.conn_local[t.conn_begin + (size_t)a * te + i] + 1]++;
                     for (size_t l = 0; l < nn; ++l) cnt[l + 1] += cnt[l];
@@ -371,49 +462,36 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                 for (int32_t g : nodes) local[g] = -1;
                 cr.nl_cap = std::max(cr.nl_cap, (int)nodes.size());
                 hb.tiles.push_back(t);
-                elem_cursor += end - pos;
-                pos = end;
+                elem_cursor += (int64_t)grp.size();
             }
         }
         cr.tile_count = (int)hb.tiles.size() - cr.tile_begin;
-        cr.nl_cap = (cr.nl_cap + 1) & ~1;
         if (cr.tile_count > 0) hb.classes.push_back(cr);
     }
-    // owner of every local node: interior nodes are written by their tile,
-    // shared nodes get one partial slot per tile, summed in tile order
-    std::vector<std::vector<int32_t>> parts_of;   // indexed through halo index
-    std::vector<int32_t> halo_index(n_nodes, -1);
-    int32_t n_halo = 0;
+    // Nodes in exactly one tile are written by that tile.  Every other node
+    // (shared, or touched by no element) gets the contiguous partial slots
+    // [halo_ptr[h], halo_ptr[h+1]), one per tile that holds it, in tile
+    // order; the shared-node kernel sums them in that order.
+    std::vector<int32_t> halo_index(n_nodes, -1), next_slot;
     for (int64_t g = 0; g < n_nodes; ++g)
-        if (tile_count[g] != 1) halo_index[g] = n_halo++;
-    parts_of.resize(n_halo);
+        if (tile_count[g] != 1) {
+            halo_index[g] = (int32_t)hb.halo_gid.size();
+            hb.halo_gid.push_back((int32_t)g);
+            hb.halo_ptr.push_back((int32_t)hb.n_part);
+            next_slot.push_back((int32_t)hb.n_part);
+            hb.n_part += tile_count[g];
+            if (hb.n_part >= INT32_MAX) return fail(TLFEA_E_SHAPE, "too many shared-node partials");
+        }
+    hb.halo_ptr.push_back((int32_t)hb.n_part);
     hb.lnode_dst.resize(hb.lnode_gid.size());
-    int64_t n_part = 0;
     for (size_t t = 0; t < hb.tiles.size(); ++t) {
         const TileDesc &T = hb.tiles[t];
         for (int l = 0; l < T.n_node; ++l) {
             const int32_t g = hb.lnode_gid[T.node_begin + l];
-            if (tile_count[g] == 1) {
-                hb.lnode_dst[T.node_begin + l] = g;
-            } else {
-                if (n_part >= INT32_MAX) return fail(TLFEA_E_SHAPE, "too many shared-node partials");
-                parts_of[halo_index[g]].push_back((int32_t)n_part);
-                hb.lnode_dst[T.node_begin + l] = -1 - (int32_t)n_part;
-                ++n_part;
-            }
+            if (tile_count[g] == 1) hb.lnode_dst[T.node_begin + l] = g;
+            else hb.lnode_dst[T.node_begin + l] = -1 - next_slot[halo_index[g]]++;
         }
     }
-    hb.n_part = n_part;
-    hb.halo_gid.reserve(n_halo);
-    hb.halo_ptr.reserve(n_halo + 1);
-    for (int64_t g = 0; g < n_nodes; ++g) {
-        const int32_t h = halo_index[g];
-        if (h < 0) continue;
-        hb.halo_gid.push_back((int32_t)g);
-        hb.halo_ptr.push_back((int32_t)hb.halo_slot.size());
-        for (int32_t p : parts_of[h]) hb.halo_slot.push_back(p);
-    }
-    hb.halo_ptr.push_back((int32_t)hb.halo_slot.size());
     return TLFEA_OK;
 }
 
@@ -461,19 +539,19 @@ static tlfea_status validate_args(int64_t n_nodes, const double *X, int32_t n_bl
 static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_blocks, const tlfea_block *blocks,
                                 int32_t flags, const std::vector<int> &te_of_block, tlfea_mesh **out)
 {
-    // LDS per workgroup: the device's limit, at most 64 KiB so two
-    // workgroups of the largest tiles can share one compute unit
-    int64_t lds_limit = 65536;
+    // LDS a workgroup may allocate on this device (the tangent of a damped
+    // block, whose node record is the widest, may use all of it)
+    int64_t lds_dev = 65536;
     {
         int dev = 0, lim = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 0)
-            lds_limit = std::min<int64_t>(lds_limit, lim);
+            lds_dev = lim;
         else
             (void)hipGetLastError();
     }
     HostBuild hb;
-    tlfea_status st = build_tiles(n_nodes, X, n_blocks, blocks, flags, te_of_block, lds_limit, hb);
+    tlfea_status st = build_tiles(n_nodes, X, n_blocks, blocks, flags, te_of_block, lds_dev, hb);
     if (st != TLFEA_OK) return st;
     tlfea_mesh *m = new (std::nothrow) tlfea_mesh();
     if (!m) return fail(TLFEA_E_NOMEM, "host allocation failed");
@@ -518,7 +596,6 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
     UP(Xv, d.X);
     UP(hb.halo_gid, d.halo_gid);
     UP(hb.halo_ptr, d.halo_ptr);
-    UP(hb.halo_slot, d.halo_slot);
 #undef UP
     d.n_nodes = n_nodes;
     d.n_elem = m->n_elem;
@@ -545,13 +622,9 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
 
 static size_t lds_bytes(const ClassRange &c, int op)
 {
-    int arrays = 2;   // X, x
-    if (op == kOpFwd) arrays += c.damped;                 // v
-    else if (op == kOpVjp) arrays += 1 + c.damped;        // w, v
-    else arrays += 1 + 2 * c.damped;                      // dx, v, dv
-    const size_t stage = (size_t)arrays * 3 * c.nl_cap * sizeof(double);
-    const size_t fe = (size_t)3 * nen_of(c.elem) * c.te * sizeof(double);
-    return std::max(stage, fe);
+    const size_t records = (size_t)c.nl_cap * record_len(op, c.damped != 0) * sizeof(double);
+    const size_t slots = (size_t)nen_of(c.elem) * c.te * sizeof(double);
+    return std::max(records, slots);
 }
 
 static tlfea_status enqueue(tlfea_mesh *m, int op, const CallArgs &c, hipStream_t s, bool timed)
@@ -566,7 +639,7 @@ static tlfea_status enqueue(tlfea_mesh *m, int op, const CallArgs &c, hipStream_
             HIP_TRY(hipEventRecord(e0, s));
         }
         hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, s, m->dm, c,
-                                    cr.tile_begin, cr.nl_cap);
+                                    cr.tile_begin);
         if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "tile kernel launch: %s", hipGetErrorString(e));
         if (timed) {
             HIP_TRY(hipEventRecord(e1, s));
@@ -720,7 +793,7 @@ static tlfea_status time_classes(tlfea_mesh *m, std::vector<double> &t_cls)
             for (int rep = 0; rep < 4; ++rep) {
                 HIP_TRY(hipEventRecord(e0, nullptr));
                 hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, nullptr, m->dm,
-                                            c, cr.tile_begin, cr.nl_cap);
+                                            c, cr.tile_begin);
                 if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "autotune launch: %s", hipGetErrorString(e));
                 HIP_TRY(hipEventRecord(e1, nullptr));
                 HIP_TRY(hipEventSynchronize(e1));

@@ -11,14 +11,16 @@ struct TileDesc {
     int32_t elem_begin;   // first internal element of the tile
     int32_t n_elem;       // elements in the tile (<= te)
     int32_t node_begin;   // first entry in lnode_gid / lnode_dst
-    int32_t n_node;       // distinct nodes of the tile
+    int32_t n_node;       // distinct nodes of the tile (<= kStagePerThread * te)
     int32_t ptr_begin;    // first entry of this tile's lnode_ptr (n_node + 1 entries)
     int32_t conn_begin;   // first entry of this tile's conn_local ([nen][te])
     int32_t block;        // owning block
-    int32_t flags;        // bit 0: every element has an affine parent map
+    int32_t pad;
 };
 
-enum { kTileAffine = 1 };
+// Node records a thread stages at most: a tile holds at most this many
+// nodes per thread of its workgroup.
+constexpr int kStagePerThread = 3;
 
 struct BlockDesc {
     double theta[5];
@@ -36,10 +38,9 @@ struct DevMesh {
     const int32_t *elem_uid;      // caller's element id of each internal element
     const BlockDesc *blocks;
     const double *X;              // [3][n_nodes]
-    const int32_t *halo_gid;      // nodes summed from partials (and orphans)
-    const int32_t *halo_ptr;      // [n_halo + 1]
-    const int32_t *halo_slot;     // partial slots, tile order
-    double *part;                 // [6][n_part] partial node sums
+    const int32_t *halo_gid;      // nodes summed from partials (and nodes no element touches)
+    const int32_t *halo_ptr;      // [n_halo + 1]: node h owns partial slots [halo_ptr[h], halo_ptr[h+1])
+    double *part;                 // [6][n_part] partial node sums (two fields x three components)
     int64_t n_nodes, n_elem, n_part, n_halo;
 };
 
@@ -51,5 +52,18 @@ struct CallArgs {
 };
 
 enum { kOpFwd = 0, kOpVjp = 1, kOpJvp = 2 };
+
+// Doubles a node record of an operation holds: X and x, plus w (adjoint) or
+// dx (tangent), plus v when damped, plus dv for the damped tangent.
+constexpr int record_fields_len(int op, bool damped)
+{
+    return 6 + (op != kOpFwd ? 3 : 0) + (damped ? 3 : 0) + ((damped && op == kOpJvp) ? 3 : 0);
+}
+
+// LDS stride of a node record, rounded up to an odd number of doubles: a
+// wavefront gathers one component of 64 unrelated nodes, and with a stride
+// of 2 x odd dwords the record starts spread over every other bank instead
+// of a quarter or an eighth of them.
+constexpr int record_len(int op, bool damped) { return record_fields_len(op, damped) | 1; }
 
 }  // namespace tlfea

@@ -17,14 +17,15 @@ namespace tlfea {
 
 hipError_t TLFEA_CAT(launch_tiles, TLFEA_ELEM, TLFEA_OP)(int law, int damped, int te, int n_tiles, size_t lds,
                                                           hipStream_t s, const DevMesh &m, const CallArgs &c,
-                                                          int tile0, int NL)
+                                                          int tile0)
 {
-    return launch_class<TLFEA_OP, TLFEA_ELEM>(law, damped, te, n_tiles, lds, s, m, c, tile0, NL);
+    return launch_class<TLFEA_OP, TLFEA_ELEM>(law, damped, te, n_tiles, lds, s, m, c, tile0);
 }
 
 #if TLFEA_ELEM == 0 && TLFEA_OP == 0
-// Nodes shared between tiles (and nodes no element touches): sum the partial
-// slots in tile order.  One lane per node; up to two output fields.
+// Nodes shared between tiles (and nodes no element touches): sum the node's
+// partial slots, which are contiguous and in tile order.  One lane per node;
+// up to two output fields.
 __global__ __launch_bounds__(256) void k_halo(DevMesh m, double *out0, double *out1)
 {
     const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -36,17 +37,13 @@ __global__ __launch_bounds__(256) void k_halo(DevMesh m, double *out0, double *o
     for (int f = 0; f < 2; ++f) {
         double *out = outs[f];
         if (!out) continue;
-        const double *part = m.part + (int64_t)(3 * f) * m.n_part;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int p = p0; p < p1; ++p) {
-            const int sl = m.halo_slot[p];
-            s0 += part[sl];
-            s1 += part[m.n_part + sl];
-            s2 += part[2 * m.n_part + sl];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const double *part = m.part + (int64_t)(3 * f + r) * m.n_part;
+            double s = 0.0;
+            for (int p = p0; p < p1; ++p) s += part[p];
+            out[r * m.n_nodes + g] = s;
         }
-        out[g] = s0;
-        out[m.n_nodes + g] = s1;
-        out[2 * m.n_nodes + g] = s2;
     }
 }
 
