@@ -11,13 +11,23 @@ deformation, velocities N(0, 0.01 m/s), cotangent w ~ N(0, 1).  Inputs are
 resident in HBM before timing.  value = quadrature points per second of the
 whole step.
 
+With --batched the line also carries the multibody comparison: 512 bodies of
+200-50,000 elements (mixed T10 / H8, SVK / Neo-Hookean), forward internal
+force of every body, timed as one batched mesh (one hipGraph replay) and as
+one plain mesh per body launched back to back on one stream.
+
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+
+--pmc-summary DIR writes the rocprofv3 summaries under profiles/ from the
+output folders of a kernel-trace run and two counter runs.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -28,44 +38,61 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+CSRC = os.path.join(ROOT, "paper_2602_17002_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_c2_fwd_vjp.md")
 
+T10, H8 = 0, 1
+SVK, MR, NH = 0, 1, 2
 
 # ---------------------------------------------------------------- cost model
-# Algorithmic arithmetic per quadrature point of the fused per-point
-# formulation (F = (N dS/dxi) J^{-1}, parent gradients with their structural
-# zeros removed, multiply-add = 2 flops, divide and cube root = 1 each).
-# nz = non-zero entries of the parent gradient table at the point (T10 5-point
-# rule: 12, 21, 20, 20, 19; H8 2x2x2 Gauss: 24 at every point).
-NZ = {0: [12, 21, 20, 20, 19], 1: [24] * 8}
-STRESS = {0: 129, 1: 269, 2: 96}          # SVK, MR, NH elastic stress
-VISC_FWD = {0: 84, 1: 138, 2: 138}        # Kelvin-Voigt add-on (SVK folds S_v into S)
-DSTRESS = {0: 240, 1: 520, 2: 283}        # elastic directional derivative incl. shared invariants
-GTHETA = {0: 40, 1: 60, 2: 43}
+# Arithmetic of the method per quadrature point, counted from the formulas
+# the kernels evaluate (one flop per multiply or add, a fused multiply-add
+# counts two; divide and cube root count one; symmetric results count their
+# six distinct entries).  nz = non-zero entries of the parent gradient table
+# at the point (T10 5-point rule: 12, 21, 20, 20, 19; H8 2x2x2 Gauss: 24).
+# A gathered field costs 6 nz (G = sum_a s_a g_a^T), the scatter 6 nz.
+NZ = {T10: [12, 21, 20, 20, 19], H8: [24] * 8}
+GEOM = 33            # cofactor of J (27) + det (5) + reciprocal (1)
+TOREF = 54           # A = (G cof(J)^T) / det J for one field
+TOPAR = 54           # Q = w_q P cof(J)
+# elastic stress (forward): SVK C, tr E, S, F S; MR/NH invariants, cof F, J, J^-2/3, ...
+STRESS = {SVK: 98, MR: 241, NH: 97}
+# Kelvin-Voigt add-on of the forward: Edot = sym(F^T Fdot) (57), S_v (14),
+# F S_v (45) and the add (9); SVK adds S_v to S instead (57 + 14 + 6)
+VISC_FWD = {SVK: 77, MR: 125, NH: 125}
+# elastic directional derivative (adjoint and tangent), invariants included
+DSTRESS = {SVK: 229, MR: 771, NH: 269}
+# w . dP/dtheta of the elastic rows; SVK also needs Gw : F (17), which the
+# Mooney-Rivlin derivative already forms
+GTHETA = {SVK: 152, MR: 53, NH: 28}
+VISC_VJP = 374       # viscous adjoint in x and v, viscous parameter rows, gv to the parent (no gathers/scatter)
+VISC_JVP = 304       # viscous tangent in x and v (no gathers)
 
 
 def flops_per_element(op, elem, law, damped):
-    nz = NZ[elem]
-    per_elem = 6 * nz[0] + 43             # J = U G at one point and its inverse (affine map)
+    """Counted FP64 arithmetic of one element (all quadrature points)."""
     tot = 0
-    for z in nz:
-        g = 6 * z                          # one gathered field -> 3x3 (3 z multiply-adds)
+    for z in NZ[elem]:
+        g = 6 * z
+        q = g + GEOM                               # reference geometry at the point
         if op == "fwd":
-            q = 2 * g if damped else g     # x (and v)
-            q += 54 * (2 if damped else 1) # times J^{-1}
+            q += (g + TOREF) * (2 if damped else 1)   # F (and Fdot)
             q += STRESS[law] + (VISC_FWD[law] if damped else 0)
-            q += 63 + g                    # c P J^{-T} and scatter to nodes
+            q += TOPAR + g                             # scatter to the nodes
         elif op == "vjp":
-            q = (3 if damped else 2) * (g + 54)   # x, w (, v) -> 3x3
-            q += DSTRESS[law] + GTHETA[law]
-            q += 63 + g                           # gx
+            q += 2 * (g + TOREF)                       # F, Gw
+            q += DSTRESS[law] + GTHETA[law] + 1 + TOPAR + g
             if damped:
-                q += 354 + 63 + g                 # viscous adjoint and gv
-        else:  # jvp
-            q = (4 if damped else 2) * (g + 54)   # x, dx (, v, dv)
-            q += DSTRESS[law] + (250 if damped else 0) + 63 + g
+                q += g + TOREF + VISC_VJP + g          # Fdot, viscous terms, gv scatter
+        else:
+            q += 2 * (g + TOREF)                       # F, dF
+            q += DSTRESS[law] + TOPAR + g
+            if damped:
+                q += 2 * (g + TOREF) + VISC_JVP        # Fdot, dFdot
         tot += q
-    return per_elem + tot
+    return tot
 
 
 def bytes_per_call(op, n_nodes, n_elem, nen, damped, theta_rows=0, gtheta=False):
@@ -88,6 +115,35 @@ def bytes_per_call(op, n_nodes, n_elem, nen, damped, theta_rows=0, gtheta=False)
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    """sha256 of the HIP library sources (ties counter summaries to a build)."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        if p.endswith((".h", ".hip", ".cpp")):
+            h.update(os.path.basename(p).encode())
+            with open(p, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_from_profile(kernel_key):
+    """HBM bytes per launch (fetch + write, copy-calibrated) of the kernel
+    from the committed counter summary, if it was taken on these sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src, rows = None, {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("SOURCE_SHA256 "):
+                src = line.split()[1]
+            elif line.startswith("TRAFFIC "):
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+                rows[kv["kernel"]] = float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+    if src != source_hash():
+        return None
+    return rows.get(kernel_key)
 
 
 def cpu_baseline(prob, budget_s=15.0):
@@ -115,17 +171,144 @@ def cpu_baseline(prob, budget_s=15.0):
                       f"({nq} quadrature points), serial C oracle, {t:.1f} s"}
 
 
+def batched_vs_plain(steps, warmup):
+    """Forward internal force of a 512-body multibody set: one batched mesh
+    (hipGraph replay) against one plain mesh per body on the same stream."""
+    import copy
+
+    import torch
+
+    import synth
+    from paper_2602_17002_amd import BATCHED, Mesh
+    t0 = time.time()
+    p = synth.config_c3()
+    log(f"[bench] C3: {len(p.blocks)} bodies, {p.n_elem} elements, {p.n_nodes} nodes ({time.time() - t0:.1f} s)")
+    dev = torch.device("cuda", 0)
+    s = torch.cuda.Stream(device=dev)
+    t0 = time.time()
+    batched = Mesh(p.X, [copy.copy(b) for b in p.blocks], flags=BATCHED)
+    plains = []
+    for bi, b in enumerate(p.blocks):
+        n0, n1 = p.body_nodes[bi]
+        bb = copy.copy(b)
+        bb.conn = b.conn - n0
+        plains.append((Mesh(p.X[:, n0:n1], [bb]), n0, n1))
+    log(f"[bench] C3 meshes built in {time.time() - t0:.1f} s")
+    with torch.cuda.stream(s):
+        x = torch.from_numpy(p.x).to(dev)
+        f_b = torch.empty_like(x)
+        xs = [x[:, n0:n1].contiguous() for _, n0, n1 in plains]
+        fs = [torch.empty_like(xx) for xx in xs]
+
+        def run_batched():
+            batched.internal_force(x, out=f_b)
+
+        def run_plain():
+            for (m, _, _), xx, ff in zip(plains, xs, fs):
+                m.internal_force(xx, out=ff)
+
+        res = {}
+        for name, fn in (("batched", run_batched), ("plain", run_plain)):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(steps):
+                fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            res[name] = e0.elapsed_time(e1) / steps
+        same = all(torch.equal(f_b[:, n0:n1], ff) for (_, n0, n1), ff in zip(plains, fs))
+    return {"workload": f"C3: {len(p.blocks)} bodies of 200-50,000 elements, mixed T10/H8, SVK/NH, "
+                        f"{p.n_elem} elements, forward f_int",
+            "ms_batched": round(res["batched"], 4), "ms_plain": round(res["plain"], 4),
+            "speedup": round(res["plain"] / res["batched"], 3),
+            "quad_pts_per_s_batched": p.n_qp / (res["batched"] * 1e-3),
+            "bitwise_equal_per_body": bool(same)}
+
+
+# ---------------------------------------------------------------- profiler summaries
+
+def _csv_rows(pattern):
+    rows = []
+    for p in sorted(glob.glob(pattern, recursive=True)):
+        with open(p) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def pmc_summary(trace_dir, fetch_dir, write_dir, commands):
+    """Write profiles/ summaries from rocprofv3 output folders: the kernel
+    statistics of a --kernel-trace --stats run, and FETCH_SIZE / WRITE_SIZE
+    per dispatch from two --pmc runs, scaled by what the same counters read
+    for the device-to-device copy kernel of known size in those runs."""
+    os.makedirs(PROFILES, exist_ok=True)
+    stats = _csv_rows(os.path.join(trace_dir, "**", "*kernel_stats.csv"))
+    lines = ["# Kernel statistics: C2 forward + adjoint (1,020,000 T10, Neo-Hookean + Kelvin-Voigt)", "",
+             f"Command: `{commands['trace']}`", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
+    with open(os.path.join(PROFILES, "kernel_stats_c2_fwd_vjp.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    def per_kernel(d, counter):
+        acc = {}
+        for r in _csv_rows(os.path.join(d, "**", "*counter_collection.csv")):
+            if r["Counter_Name"] != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return acc
+
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    copy_name = next(k for k in fetch if "copyBuffer" in k)
+    calib_kib = float(commands["calib_mib"]) * 1024.0
+    f_scale = calib_kib / max(fetch[copy_name])
+    w_scale = calib_kib / max(write[copy_name])
+    lines = ["# HBM traffic per dispatch: C2 forward + adjoint (1,020,000 T10, Neo-Hookean + Kelvin-Voigt)", "",
+             f"Fetch command: `{commands['fetch']}`", "", f"Write command: `{commands['write']}`", "",
+             f"Calibration: the {commands['calib_mib']} MiB device-to-device copy (`{copy_name}`) read "
+             f"FETCH_SIZE {max(fetch[copy_name]):.0f} KiB and WRITE_SIZE {max(write[copy_name]):.0f} KiB; "
+             f"scale factors {f_scale:.3f} (fetch) and {w_scale:.3f} (write).", "",
+             "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | fetch MB (scaled) | write MB (scaled) |",
+             "|---|---|---|---|---|---|"]
+    machine = [f"SOURCE_SHA256 {source_hash()}"]
+    for k in sorted(fetch):
+        if "tlfea" not in k:
+            continue
+        fk = float(np.median(fetch[k]))
+        wk = float(np.median(write.get(k, [0.0])))
+        fb, wb = fk * 1024 * f_scale, wk * 1024 * w_scale
+        lines.append(f"| `{k[:80]}` | {len(fetch[k])} | {fk:.0f} | {wk:.0f} | {fb / 1e6:.1f} | {wb / 1e6:.1f} |")
+        key = k.split("(")[0].replace("void ", "").replace(" ", "")
+        machine.append(f"TRAFFIC kernel={key} fetch_bytes={fb:.0f} write_bytes={wb:.0f}")
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n\n```\n" + "\n".join(machine) + "\n```\n")
+    print("\n".join(machine))
+
+
+# ---------------------------------------------------------------- main
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", action="store_true", help="also time the 512-body batched vs plain comparison")
     ap.add_argument("--tile", type=int, default=0, help="elements per tile (0 = library default)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of known "
                          "traffic, used to scale the HBM byte counters of a profiler run)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--commands", default="{}", help="JSON: the profiler command lines (for --pmc-summary)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, json.loads(args.commands))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
@@ -169,19 +352,23 @@ def main():
 
         for _ in range(args.warmup):
             step()
+        # whole steps (the value)
         torch.cuda.synchronize()
-        mesh.reset_profile()
-        mesh.set_profiling(True)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
         e0.record(stream)
         for _ in range(args.steps):
             step()
         e1.record(stream)
         torch.cuda.synchronize()
-        mesh.set_profiling(False)
         ms_total = e0.elapsed_time(e1)
+        # per-kernel durations (HIP events around every launch, on the launch stream)
+        mesh.reset_profile()
+        mesh.set_profiling(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        mesh.set_profiling(False)
         prof = mesh.profile()
     log(f"[bench] timed {args.steps} steps: {ms_total:.3f} ms; kernels {prof}")
     ms_step = ms_total / args.steps
@@ -193,15 +380,18 @@ def main():
     dom = max(("forward_tile", "adjoint_tile"), key=lambda k: k_ms[k][1])
     op = "fwd" if dom == "forward_tile" else "vjp"
     ne, nn = prob.n_elem, prob.n_nodes
-    flops = flops_per_element(op, synth.T10, synth.NH, True) * ne
+    fpe = flops_per_element(op, T10, NH, True)
+    flops = fpe * ne
     t_dom = k_ms[dom][1] * 1e-3
     achieved = flops / t_dom / 1e12
     byts = bytes_per_call(op, nn, ne, 10, True)
+    kname = "tlfea::k_fwd<0,2,true>" if op == "fwd" else "tlfea::k_vjp<0,2,true>"
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-            "kernel": dom, "kernel_ms": round(k_ms[dom][1], 4),
-            "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byts,
-            "hbm_frac": round(byts / t_dom / 1e9 / HBM_PEAK_GBS, 4)}
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic_from_profile(kname),
+            "kernel": kname, "kernel_ms": round(k_ms[dom][1], 4),
+            "flops_per_element": fpe, "elements_per_launch": ne,
+            "algorithmic_bytes_per_launch": byts,
+            "hbm_frac_algorithmic": round(byts / t_dom / 1e9 / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": "quad-pts/s f_int fwd+VJP (1M T10 NH), batched vs plain; % HBM/FP64 peak",
@@ -214,6 +404,8 @@ def main():
         "kernels_ms_avg": {k: round(t, 4) for k, (c, t) in k_ms.items() if c},
         "roofline": roof,
     }
+    if args.batched:
+        out["batched_vs_plain"] = batched_vs_plain(max(3, args.steps // 4), 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -90,7 +90,7 @@ typedef struct {
     const int32_t *conn;     /* HOST [n_elem][nen], 0-based global node ids    */
     double theta[5];         /* default parameter rows (used when theta==NULL) */
     int32_t damped;          /* nonzero: Kelvin-Voigt branch active            */
-    int32_t tile_elems;      /* elements per tile: 0 = default, else 64/128/256*/
+    int32_t tile_elems;      /* elements per tile: 0 = default, else 64/128/192/256 */
 } tlfea_block;
 
 typedef struct {

@@ -659,20 +659,81 @@ __device__ __forceinline__ void load_na(const DevMesh &m, const TileDesc &t, int
     for (int a = 0; a < NEN; ++a) na[a] = (int)m.conn_local[t.conn_begin + a * te + i] * LEN;
 }
 
+// The tile's assembly tables, copied to LDS while the node records are
+// staged: for every local node its CSR range of element slots and its
+// destination (>= 0: global node written directly; < 0: -1 - partial slot).
+struct TileCsr {
+    int32_t *ptr;      // [n_node + 1], relative to the tile's first entry
+    int32_t *dst;      // [n_node]
+    uint16_t *slot;    // [nen * n_elem]: element slot a * te + i of each entry
+};
+
+// LDS layout of a tile: the node records (later overwritten by the element
+// slots of one component), then the assembly tables.
+__device__ __forceinline__ TileCsr csr_layout(double *smem, int nl, int rec_len, int nen, int te)
+{
+    const int a = max(nl * rec_len, nen * te);   // doubles
+    TileCsr c;
+    c.ptr = reinterpret_cast<int32_t *>(smem + a);
+    c.dst = c.ptr + nl + 1;
+    c.slot = reinterpret_cast<uint16_t *>(c.dst + nl);
+    return c;
+}
+
+// Every load of a thread is issued before its LDS stores (a loop of
+// load-then-store would wait for one global round trip per iteration).  The
+// slot ids are copied as 32-bit words; a tile's entries start at an even
+// global index (the host pads every tile's list to an even length).
+template <int NEN>
+__device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, const TileDesc &t, int tid, int nthr)
+{
+    const int32_t *gptr = m.lnode_ptr + t.ptr_begin;
+    const int32_t base = gptr[0];
+    int32_t pv[kStagePerThread + 1], dv[kStagePerThread];
+#pragma unroll
+    for (int k = 0; k <= kStagePerThread; ++k) {
+        const int l = tid + k * nthr;
+        pv[k] = l <= t.n_node ? gptr[l] - base : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kStagePerThread; ++k) {
+        const int l = tid + k * nthr;
+        dv[k] = l < t.n_node ? m.lnode_dst[t.node_begin + l] : 0;
+    }
+    // NEN * n_elem entries = NEN * n_elem / 2 words; at most NEN / 2 words per thread
+    constexpr int W = (NEN + 1) / 2;
+    const int n_words = (NEN * t.n_elem + 1) / 2;
+    const uint32_t *gw = reinterpret_cast<const uint32_t *>(m.lnode_slot + base);
+    uint32_t wv[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int e = tid + k * nthr;
+        wv[k] = e < n_words ? gw[e] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k <= kStagePerThread; ++k)
+        if (tid + k * nthr <= t.n_node) c.ptr[tid + k * nthr] = pv[k];
+#pragma unroll
+    for (int k = 0; k < kStagePerThread; ++k)
+        if (tid + k * nthr < t.n_node) c.dst[tid + k * nthr] = dv[k];
+    uint32_t *sw = reinterpret_cast<uint32_t *>(c.slot);
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        if (tid + k * nthr < n_words) sw[tid + k * nthr] = wv[k];
+}
+
 // Sum, for every local node, its element slots (CSR order) of one component
 // and write the value to the output (node owned by this tile only) or to the
 // node's partial slot in row `row` of the partial buffer (shared node).
-__device__ __forceinline__ void reduce_component(const DevMesh &m, const TileDesc &t,
+__device__ __forceinline__ void reduce_component(const DevMesh &m, const TileDesc &t, const TileCsr &c,
                                                  const double *__restrict__ slot, double *__restrict__ out,
                                                  int row, int comp, int tid, int nthr)
 {
-    const int32_t *ptr = m.lnode_ptr + t.ptr_begin;
-    const int32_t *dst = m.lnode_dst + t.node_begin;
     for (int l = tid; l < t.n_node; l += nthr) {
-        const int p0 = ptr[l], p1 = ptr[l + 1];
+        const int p0 = c.ptr[l], p1 = c.ptr[l + 1];
         double s = 0.0;
-        for (int p = p0; p < p1; ++p) s += slot[m.lnode_slot[p]];
-        const int d = dst[l];
+        for (int p = p0; p < p1; ++p) s += slot[c.slot[p]];
+        const int d = c.dst[l];
         if (d >= 0) out[comp * m.n_nodes + d] = s;
         else m.part[(int64_t)row * m.n_part + (-1 - d)] = s;
     }
@@ -682,9 +743,9 @@ __device__ __forceinline__ void reduce_component(const DevMesh &m, const TileDes
 // a time so that the LDS slots (a * te + i) need NEN x te doubles only; the
 // slots overwrite the node records, which are dead once every lane is done.
 template <int NEN>
-__device__ __forceinline__ void assemble(const DevMesh &m, const TileDesc &t, double *__restrict__ sm,
-                                         const double (&fe)[NEN][3], bool active, double *__restrict__ out,
-                                         int field, int tid, int te)
+__device__ __forceinline__ void assemble(const DevMesh &m, const TileDesc &t, const TileCsr &c,
+                                         double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
+                                         double *__restrict__ out, int field, int tid, int te)
 {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -694,18 +755,17 @@ __device__ __forceinline__ void assemble(const DevMesh &m, const TileDesc &t, do
             for (int a = 0; a < NEN; ++a) sm[a * te + tid] = fe[a][r];
         }
         __syncthreads();
-        reduce_component(m, t, sm, out, 3 * field + r, r, tid, te);
+        reduce_component(m, t, c, sm, out, 3 * field + r, r, tid, te);
     }
 }
 
 // Zeros for every destination of the tile's nodes (an undamped tile's share
 // of the velocity adjoint).
-__device__ __forceinline__ void zero_nodes(const DevMesh &m, const TileDesc &t, double *__restrict__ out, int field,
-                                           int tid, int nthr)
+__device__ __forceinline__ void zero_nodes(const DevMesh &m, const TileDesc &t, const TileCsr &c,
+                                           double *__restrict__ out, int field, int tid, int nthr)
 {
-    const int32_t *dst = m.lnode_dst + t.node_begin;
     for (int l = tid; l < t.n_node; l += nthr) {
-        const int d = dst[l];
+        const int d = c.dst[l];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             if (d >= 0) out[r * m.n_nodes + d] = 0.0;
@@ -719,7 +779,7 @@ __device__ __forceinline__ void zero_nodes(const DevMesh &m, const TileDesc &t, 
 #define TLFEA_MAX_TE 256
 
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LAW == 1 ? 2 : 3))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LAW == 1 ? 2 : 3))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpFwd, DAMPED>;
@@ -728,6 +788,8 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LA
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
+    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te);
+    stage_csr<NEN>(csr, m, t, tid, te);
     stage_tile<kOpFwd, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
     double fe[NEN][3];
@@ -741,11 +803,11 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LA
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
         fwd_element<ELEM, LAW, DAMPED>(smem, na, mt, fe);
     }
-    assemble<NEN>(m, t, smem, fe, active, c.out0, 0, tid, te);
+    assemble<NEN>(m, t, csr, smem, fe, active, c.out0, 0, tid, te);
 }
 
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpVjp, DAMPED>;
@@ -754,6 +816,8 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2)
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
+    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te);
+    stage_csr<NEN>(csr, m, t, tid, te);
     stage_tile<kOpVjp, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
     double gx[NEN][3], gv[NEN][3], gt[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -777,17 +841,17 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2)
             c.gtheta[4 * m.n_elem + uid] = DAMPED ? gt[4] : 0.0;
         }
     }
-    if (c.out0) assemble<NEN>(m, t, smem, gx, active, c.out0, 0, tid, te);
+    if (c.out0) assemble<NEN>(m, t, csr, smem, gx, active, c.out0, 0, tid, te);
     if (c.out1) {
-        if constexpr (DAMPED) assemble<NEN>(m, t, smem, gv, active, c.out1, 1, tid, te);
-        else zero_nodes(m, t, c.out1, 1, tid, te);
+        if constexpr (DAMPED) assemble<NEN>(m, t, csr, smem, gv, active, c.out1, 1, tid, te);
+        else zero_nodes(m, t, csr, c.out1, 1, tid, te);
     }
 }
 
 // The tangent stages dx (zeros when null) and, for damped blocks, dv (zeros
 // when null), so one instantiation serves every combination.
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te)
+__global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpJvp, DAMPED>;
@@ -796,6 +860,8 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
+    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te);
+    stage_csr<NEN>(csr, m, t, tid, te);
     stage_tile<kOpJvp, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
     double df[NEN][3];
@@ -809,33 +875,33 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
         jvp_element<ELEM, LAW, DAMPED>(smem, na, mt, df);
     }
-    assemble<NEN>(m, t, smem, df, active, c.out0, 0, tid, te);
+    assemble<NEN>(m, t, csr, smem, df, active, c.out0, 0, tid, te);
 }
 
 template <int OP, int ELEM, int LAW, bool DAMPED>
 hipError_t launch_one(dim3 grid, int te, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c, int tile0,
-                      int ntile)
+                      int ntile, int nl)
 {
-    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te);
-    else if constexpr (OP == kOpVjp) k_vjp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te);
-    else k_jvp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te);
+    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl);
+    else if constexpr (OP == kOpVjp) k_vjp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl);
+    else k_jvp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl);
     return hipGetLastError();
 }
 
 template <int OP, int ELEM>
 hipError_t launch_class(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m,
-                        const CallArgs &c, int tile0)
+                        const CallArgs &c, int tile0, int nl)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
     switch (law * 2 + (damped ? 1 : 0)) {
-    case 0: return launch_one<OP, ELEM, 0, false>(grid, te, lds, s, m, c, tile0, n_tiles);
-    case 1: return launch_one<OP, ELEM, 0, true>(grid, te, lds, s, m, c, tile0, n_tiles);
-    case 2: return launch_one<OP, ELEM, 1, false>(grid, te, lds, s, m, c, tile0, n_tiles);
-    case 3: return launch_one<OP, ELEM, 1, true>(grid, te, lds, s, m, c, tile0, n_tiles);
-    case 4: return launch_one<OP, ELEM, 2, false>(grid, te, lds, s, m, c, tile0, n_tiles);
-    case 5: return launch_one<OP, ELEM, 2, true>(grid, te, lds, s, m, c, tile0, n_tiles);
+    case 0: return launch_one<OP, ELEM, 0, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
+    case 1: return launch_one<OP, ELEM, 0, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
+    case 2: return launch_one<OP, ELEM, 1, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
+    case 3: return launch_one<OP, ELEM, 1, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
+    case 4: return launch_one<OP, ELEM, 2, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
+    case 5: return launch_one<OP, ELEM, 2, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
     default: return hipErrorInvalidValue;
     }
 }

@@ -21,7 +21,7 @@
 namespace tlfea {
 #define TLFEA_DECL(e, o)                                                                                   \
     hipError_t launch_tiles_e##e##_o##o(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, \
-                                        const DevMesh &m, const CallArgs &c, int tile0);
+                                        const DevMesh &m, const CallArgs &c, int tile0, int nl);
 TLFEA_DECL(0, 0)
 TLFEA_DECL(0, 1)
 TLFEA_DECL(0, 2)
@@ -32,13 +32,13 @@ TLFEA_DECL(1, 2)
 hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1);
 
 static hipError_t launch_tiles(int elem, int law, int damped, int te, int op, int n_tiles, size_t lds, hipStream_t s,
-                               const DevMesh &m, const CallArgs &c, int tile0)
+                               const DevMesh &m, const CallArgs &c, int tile0, int nl)
 {
-    typedef hipError_t (*fn_t)(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int);
+    typedef hipError_t (*fn_t)(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int);
     static const fn_t table[2][3] = {{launch_tiles_e0_o0, launch_tiles_e0_o1, launch_tiles_e0_o2},
                                      {launch_tiles_e1_o0, launch_tiles_e1_o1, launch_tiles_e1_o2}};
     if (elem < 0 || elem > 1 || op < 0 || op > 2) return hipErrorInvalidValue;
-    return table[elem][op](law, damped, te, n_tiles, lds, s, m, c, tile0);
+    return table[elem][op](law, damped, te, n_tiles, lds, s, m, c, tile0, nl);
 }
 }  // namespace tlfea
 
@@ -237,13 +237,23 @@ struct HostBuild {
 static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
 
 // Distinct nodes a tile may hold: at most kStagePerThread per thread, and
-// few enough that the node records of the forward and adjoint fit 64 KiB of
-// LDS and those of the tangent (the widest record) fit the device's limit.
-static int nl_limit(int te, int damped, int64_t lds_dev)
+// few enough that every operation's LDS (node records plus assembly tables,
+// see lds_bytes) stays within its budget: the device's per-workgroup limit,
+// and at most the share of a 160 KiB compute-unit LDS that lets the
+// workgroups the kernel's register use allows (three for the forward, two
+// for the adjoint and the tangent) be resident together.
+static int nl_limit(int elem, int te, int damped, int64_t lds_dev)
 {
-    const int64_t fv = 65536 / (8 * (int64_t)record_len(kOpVjp, damped != 0));
-    const int64_t jv = lds_dev / (8 * (int64_t)record_len(kOpJvp, damped != 0));
-    return (int)std::min<int64_t>((int64_t)kStagePerThread * te, std::min(fv, jv));
+    const int nen = nen_of(elem);
+    int64_t nl = (int64_t)kStagePerThread * te;
+    const int wgs[3] = {3, 2, 2};
+    for (int op = kOpFwd; op <= kOpJvp; ++op) {
+        const int64_t budget = std::min<int64_t>(lds_dev, 163840 / wgs[op]);
+        const int64_t fixed = 4 + (int64_t)nen * te * 2;
+        const int64_t per_node = 8 * (int64_t)record_len(op, damped != 0) + 8;
+        nl = std::min(nl, (budget - fixed) / per_node);
+    }
+    return (int)nl;
 }
 
 // Cut the elements `ids` (one block, Morton order) into tiles of at most te
@@ -374,7 +384,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
     for (size_t k = 0; k < keys.size(); ++k) {
         ClassRange cr{keys[k].elem, keys[k].law, keys[k].damped, keys[k].te, (int)hb.tiles.size(), 0, 0};
         const int te = keys[k].te, nen = nen_of(keys[k].elem);
-        const int nlmax = nl_limit(te, keys[k].damped, lds_dev);
+        const int nlmax = nl_limit(keys[k].elem, te, keys[k].damped, lds_dev);
         if (nlmax < nen || (int64_t)nen * te * (int64_t)sizeof(double) > 65536)
             return fail(TLFEA_E_UNSUPPORTED, "tile of %d elements does not fit the LDS of one workgroup", te);
         for (int b = 0; b < n_blocks; ++b) {
@@ -443,8 +453,10 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                     hb.elem_uid.push_back((int32_t)(uid0[b] + e));
                 }
                 // per-node slot lists (CSR); visiting slots a * te + i in
-                // increasing order leaves every list sorted
+                // increasing order leaves every list sorted.  Each tile's list
+                // starts at an even index (the kernels copy it as 32-bit words).
                 {
+                    if (hb.lnode_slot.size() & 1) hb.lnode_slot.push_back(0);
                     const size_t nn = nodes.size(), base = hb.lnode_slot.size();
                     std::vector<int32_t> cnt(nn + 1, 0);
                     const int64_t ne_t = (int64_t)grp.size();
@@ -468,6 +480,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
         cr.tile_count = (int)hb.tiles.size() - cr.tile_begin;
         if (cr.tile_count > 0) hb.classes.push_back(cr);
     }
+    if (hb.lnode_slot.size() & 1) hb.lnode_slot.push_back(0);   // whole 32-bit words
     // Nodes in exactly one tile are written by that tile.  Every other node
     // (shared, or touched by no element) gets the contiguous partial slots
     // [halo_ptr[h], halo_ptr[h+1]), one per tile that holds it, in tile
@@ -515,8 +528,8 @@ static tlfea_status validate_args(int64_t n_nodes, const double *X, int32_t n_bl
             return fail(TLFEA_E_INVALID, "block %d: unknown law %d", b, B.law);
         if (B.n_elem < 0) return fail(TLFEA_E_SHAPE, "block %d: n_elem < 0", b);
         if (B.n_elem > 0 && !B.conn) return fail(TLFEA_E_INVALID, "block %d: conn is NULL", b);
-        if (B.tile_elems != 0 && B.tile_elems != 64 && B.tile_elems != 128 && B.tile_elems != 256)
-            return fail(TLFEA_E_INVALID, "block %d: tile_elems must be 0, 64, 128 or 256", b);
+        if (B.tile_elems < 0 || B.tile_elems > 256 || (B.tile_elems & 63))
+            return fail(TLFEA_E_INVALID, "block %d: tile_elems must be 0, 64, 128, 192 or 256", b);
         for (int p = 0; p < 5; ++p)
             if (!std::isfinite(B.theta[p])) return fail(TLFEA_E_INVALID, "block %d: theta[%d] not finite", b, p);
         const int nen = nen_of(B.elem);
@@ -620,11 +633,14 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
 
 // ------------------------------------------------------------------ launching
 
+// LDS of one workgroup: the node records (reused for the element slots of
+// one component), then the tile's assembly tables (see the kernels).
 static size_t lds_bytes(const ClassRange &c, int op)
 {
-    const size_t records = (size_t)c.nl_cap * record_len(op, c.damped != 0) * sizeof(double);
-    const size_t slots = (size_t)nen_of(c.elem) * c.te * sizeof(double);
-    return std::max(records, slots);
+    const size_t records = (size_t)c.nl_cap * record_len(op, c.damped != 0);
+    const size_t slots = (size_t)nen_of(c.elem) * c.te;
+    const size_t tables = (size_t)(2 * c.nl_cap + 1) * sizeof(int32_t) + (size_t)nen_of(c.elem) * c.te * sizeof(uint16_t);
+    return std::max(records, slots) * sizeof(double) + tables;
 }
 
 static tlfea_status enqueue(tlfea_mesh *m, int op, const CallArgs &c, hipStream_t s, bool timed)
@@ -639,7 +655,7 @@ static tlfea_status enqueue(tlfea_mesh *m, int op, const CallArgs &c, hipStream_
             HIP_TRY(hipEventRecord(e0, s));
         }
         hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, s, m->dm, c,
-                                    cr.tile_begin);
+                                    cr.tile_begin, cr.nl_cap);
         if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "tile kernel launch: %s", hipGetErrorString(e));
         if (timed) {
             HIP_TRY(hipEventRecord(e1, s));
@@ -793,7 +809,7 @@ static tlfea_status time_classes(tlfea_mesh *m, std::vector<double> &t_cls)
             for (int rep = 0; rep < 4; ++rep) {
                 HIP_TRY(hipEventRecord(e0, nullptr));
                 hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, nullptr, m->dm,
-                                            c, cr.tile_begin);
+                                            c, cr.tile_begin, cr.nl_cap);
                 if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "autotune launch: %s", hipGetErrorString(e));
                 HIP_TRY(hipEventRecord(e1, nullptr));
                 HIP_TRY(hipEventSynchronize(e1));

@@ -17,9 +17,9 @@ namespace tlfea {
 
 hipError_t TLFEA_CAT(launch_tiles, TLFEA_ELEM, TLFEA_OP)(int law, int damped, int te, int n_tiles, size_t lds,
                                                           hipStream_t s, const DevMesh &m, const CallArgs &c,
-                                                          int tile0)
+                                                          int tile0, int nl)
 {
-    return launch_class<TLFEA_OP, TLFEA_ELEM>(law, damped, te, n_tiles, lds, s, m, c, tile0);
+    return launch_class<TLFEA_OP, TLFEA_ELEM>(law, damped, te, n_tiles, lds, s, m, c, tile0, nl);
 }
 
 #if TLFEA_ELEM == 0 && TLFEA_OP == 0
