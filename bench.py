@@ -11,7 +11,7 @@ deformation, velocities N(0, 0.01 m/s), cotangent w ~ N(0, 1).  Inputs are
 resident in HBM before timing.  value = quadrature points per second of the
 whole step.
 
-With --batched the line also carries the multibody comparison: 512 bodies of
+The line also carries the multibody comparison (skip with --no-batched): 512 bodies of
 200-50,000 elements (mixed T10 / H8, SVK / Neo-Hookean), forward internal
 force of every body, timed as one batched mesh (one hipGraph replay) and as
 one plain mesh per body launched back to back on one stream.
@@ -298,7 +298,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batched", action="store_true", help="also time the 512-body batched vs plain comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-body batched vs plain comparison")
     ap.add_argument("--tile", type=int, default=0, help="elements per tile (0 = library default)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of known "
@@ -404,7 +404,7 @@ def main():
         "kernels_ms_avg": {k: round(t, 4) for k, (c, t) in k_ms.items() if c},
         "roofline": roof,
     }
-    if args.batched:
+    if not args.no_batched:
         out["batched_vs_plain"] = batched_vs_plain(max(3, args.steps // 4), 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
