@@ -226,6 +226,61 @@ __device__ __forceinline__ void visc_op(const Mat &m, const m3 &A, m3 &S)   // S
         for (int j = 0; j < 3; ++j) S[i][j] = 2.0 * m.mu_v * A[i][j] + (i == j ? m.lam_v * tr : 0.0);
 }
 
+// Symmetric 3x3 matrices stored by their six distinct entries
+// (xx, yy, zz, xy, yz, xz): strain rates and viscous stresses.
+struct s3 {
+    double a[6];
+};
+
+__device__ __forceinline__ constexpr int sidx(int i, int j)
+{
+    return i == j ? i : (i + j == 1 ? 3 : (i + j == 3 ? 4 : 5));
+}
+
+// sym(F^T G) = (F^T G + G^T F) / 2
+__device__ __forceinline__ s3 sym_FtG_s(const m3 &F, const m3 &G)
+{
+    s3 S;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) t += F[k][i] * G[k][j] + F[k][j] * G[k][i];
+            S.a[sidx(i, j)] = 0.5 * t;
+        }
+    return S;
+}
+
+__device__ __forceinline__ double trace_s(const s3 &A) { return A.a[0] + A.a[1] + A.a[2]; }
+
+// S_v[A] = 2 mu_v A + lambda_v tr(A) I
+__device__ __forceinline__ s3 visc_s(const Mat &m, const s3 &A)
+{
+    const double tl = m.lam_v * trace_s(A), m2 = 2.0 * m.mu_v;
+    s3 S;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) S.a[d] = m2 * A.a[d] + (d < 3 ? tl : 0.0);
+    return S;
+}
+
+__device__ __forceinline__ double ddot_s(const s3 &A, const s3 &B)
+{
+    return A.a[0] * B.a[0] + A.a[1] * B.a[1] + A.a[2] * B.a[2] +
+           2.0 * (A.a[3] * B.a[3] + A.a[4] * B.a[4] + A.a[5] * B.a[5]);
+}
+
+// R += M S
+__device__ __forceinline__ void acc_mul_ms(const m3 &M, const s3 &S, m3 &R)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            R[i][j] += M[i][0] * S.a[sidx(0, j)] + M[i][1] * S.a[sidx(1, j)] + M[i][2] * S.a[sidx(2, j)];
+}
+
 // Invariants and pieces shared by the Mooney-Rivlin stress and its derivative.
 struct MRState {
     m3 FiT;          // F^{-T}
@@ -382,6 +437,71 @@ __device__ __forceinline__ void delastic(const m3 &F, const Mat &m, const m3 &D,
     }
 }
 
+// Scalars of the elastic derivative that the parameter gradients reuse:
+// GF = F : D, GFiT = F^{-T} : D (Mooney-Rivlin), and for SVK tr E and E : D.
+struct DerivScalars {
+    double GF, GFiT, trE, ED;
+};
+
+// A += (dP_e/dF)[D], formed without storing dP: for Neo-Hookean the term
+// F^{-T} D^T F^{-T} is added entry by entry; Mooney-Rivlin uses delastic.
+template <int LAW>
+__device__ __forceinline__ void delastic_acc(const m3 &F, const Mat &m, const m3 &D, const MRState &st, m3 &A,
+                                             DerivScalars &ds)
+{
+    if constexpr (LAW == 0) {
+        const s3 C = sym_FtG_s(F, F);                // C = F^T F
+        const double trE = 0.5 * (trace_s(C) - 3.0);
+        s3 S, dE = sym_FtG_s(F, D);                  // dE = sym(F^T D)
+        const double trdE = trace_s(dE);
+        double ED = 0.0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const double E = 0.5 * (C.a[d] - (d < 3 ? 1.0 : 0.0));
+            ED += (d < 3 ? 1.0 : 2.0) * E * dE.a[d];
+            S.a[d] = 2.0 * m.p1 * E + (d < 3 ? m.p0 * trE : 0.0);
+            dE.a[d] = 2.0 * m.p1 * dE.a[d] + (d < 3 ? m.p0 * trdE : 0.0);
+        }
+        acc_mul_ms(D, S, A);
+        acc_mul_ms(F, dE, A);
+        ds.GF = trdE;                                // F : D = tr sym(F^T D)
+        ds.GFiT = 0.0;
+        ds.trE = trE;
+        ds.ED = ED;
+    } else if constexpr (LAW == 2) {
+        const double tF = ddot(st.FiT, D);           // F^{-T} : D = dJ / J
+        const double FD = ddot(F, D);
+        const double alpha = 2.0 * m.p0 * st.J23;
+        const double dalpha = -(2.0 / 3.0) * alpha * tF;
+        const double dI1 = 2.0 * FD;
+        m3 T;                                        // T = D^T F^{-T}
+        mTm(D, st.FiT, T);
+        const double J = st.J;
+        const double cFiT = -(1.0 / 3.0) * (dalpha * st.I1 + alpha * dI1) + m.p2 * (2.0 * J - 1.0) * J * tF;
+        const double cX = (1.0 / 3.0) * alpha * st.I1 - m.p2 * (J - 1.0) * J;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double X = st.FiT[i][0] * T[0][j] + st.FiT[i][1] * T[1][j] + st.FiT[i][2] * T[2][j];
+                A[i][j] += alpha * D[i][j] + dalpha * F[i][j] + cFiT * st.FiT[i][j] + cX * X;
+            }
+        ds.GF = FD;
+        ds.GFiT = tF;
+        ds.trE = ds.ED = 0.0;
+    } else {
+        m3 dP;
+        delastic<LAW>(F, m, D, st, dP);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) A[i][j] += dP[i][j];
+        ds.GF = ddot(F, D);
+        ds.GFiT = ddot(st.FiT, D);
+        ds.trE = ds.ED = 0.0;
+    }
+}
+
 // ------------------------------------------------------------ element bodies
 
 template <int LAW>
@@ -450,7 +570,9 @@ __device__ __forceinline__ void fwd_element(const double *sm, const int (&na)[NE
 //   gx_a += c_q Fbar_x h_a, Fbar_x = (dP_e/dF)[Gw] + Gw S_v + Fdot S_v[sym(F^T Gw)]
 //   gv_a += c_q Fbar_v h_a, Fbar_v = F S_v[sym(F^T Gw)]
 //   gtheta_p += c_q Gw : dP/dtheta_p   (P is linear in every parameter row)
-template <int ELEM, int LAW, bool DAMPED, int NEN>
+// The viscous terms come first and go straight into Fbar_x and gv, so that
+// the strain rates are dead before the elastic derivative needs registers.
+template <int ELEM, int LAW, bool DAMPED, bool WANT_GT, int NEN>
 __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NEN], const Mat &mt,
                                             double (&gx)[NEN][3], double (&gv)[NEN][3], double (&gt)[5])
 {
@@ -458,7 +580,6 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
     using R = Rec<kOpVjp, DAMPED>;
     point_loop<E::nq>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        qp_fence();
         m3 K, G, F, Gw, Fb;
         double detJ, r;
         ref_geometry<ELEM, q>(sm + R::oX, na, K, detJ, r);
@@ -467,49 +588,52 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
         grad_field<ELEM, q>(sm + R::o2, na, G);
         to_reference(G, K, r, Gw);
         const double c = E::weight(q) * detJ;
-        MRState st;
-        if constexpr (LAW != 0) mr_state<LAW>(F, st);
-        delastic<LAW>(F, mt, Gw, st, Fb);
-        const double GF = ddot(Gw, F);
-        // parameter gradients
-        if constexpr (LAW == 0) {
-            m3 C, A;
-            mTm(F, F, C);
-            mTm(F, Gw, A);
-            const double trE = 0.5 * (C[0][0] + C[1][1] + C[2][2] - 3.0);
-            double EA = 0.0;
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) EA += 0.5 * (C[i][j] - (i == j ? 1.0 : 0.0)) * A[i][j];
-            gt[0] += c * trE * GF;
-            gt[1] += c * 2.0 * EA;
-        } else {
-            const double GFiT = ddot(Gw, st.FiT);
-            gt[0] += c * 2.0 * st.J23 * (GF - (1.0 / 3.0) * st.I1 * GFiT);
-            if constexpr (LAW == 1)
-                gt[1] += c * 2.0 * st.J43 * (st.I1 * GF - ddot(Gw, st.FC) - (2.0 / 3.0) * st.I2 * GFiT);
-            gt[2] += c * (st.J - 1.0) * st.J * GFiT;
-        }
+            for (int j = 0; j < 3; ++j) Fb[i][j] = 0.0;
         if constexpr (DAMPED) {
-            m3 Fd, Ed, Sv, Sg, SvSg, T, A;
+            m3 Fd;
             grad_field<ELEM, q>(sm + R::ov, na, G);
             to_reference(G, K, r, Fd);
-            sym_FtG(F, Fd, Ed);
-            visc_op(mt, Ed, Sv);
-            sym_FtG(F, Gw, Sg);
-            visc_op(mt, Sg, SvSg);             // S_v[sym(F^T Gw)]
-            gt[3] += c * 2.0 * ddot(Ed, Sg);
-            gt[4] += c * (Ed[0][0] + Ed[1][1] + Ed[2][2]) * GF;
-            mm(Gw, Sv, T);
-            mm(Fd, SvSg, A);
+            s3 Ed;
+            {
+                Ed = sym_FtG_s(F, Fd);
+                const s3 Sv = visc_s(mt, Ed);
+                acc_mul_ms(Gw, Sv, Fb);              // Gw S_v
+            }
+            {
+                const s3 Sg = sym_FtG_s(F, Gw);
+                if constexpr (WANT_GT) {
+                    gt[3] += c * 2.0 * ddot_s(Ed, Sg);
+                    gt[4] += c * trace_s(Ed) * trace_s(Sg);   // tr(Edot) (F : Gw)
+                }
+                const s3 SvSg = visc_s(mt, Sg);      // S_v[sym(F^T Gw)]
+                acc_mul_ms(Fd, SvSg, Fb);            // Fdot S_v[sym(F^T Gw)]
+                m3 A, T;
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
+                for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) Fb[i][j] += T[i][j] + A[i][j];
-            mm(F, SvSg, A);                        // Fbar_v
-            to_parent(A, K, E::weight(q), T);
-            scatter_grad<ELEM, q>(T, gv);
+                    for (int j = 0; j < 3; ++j) A[i][j] = 0.0;
+                acc_mul_ms(F, SvSg, A);              // Fbar_v
+                to_parent(A, K, E::weight(q), T);
+                scatter_grad<ELEM, q>(T, gv);
+            }
+        }
+        MRState st;
+        if constexpr (LAW != 0) mr_state<LAW>(F, st);
+        DerivScalars ds;
+        delastic_acc<LAW>(F, mt, Gw, st, Fb, ds);
+        if constexpr (WANT_GT) {
+            if constexpr (LAW == 0) {
+                gt[0] += c * ds.trE * ds.GF;
+                gt[1] += c * 2.0 * ds.ED;
+            } else {
+                gt[0] += c * 2.0 * st.J23 * (ds.GF - (1.0 / 3.0) * st.I1 * ds.GFiT);
+                if constexpr (LAW == 1)
+                    gt[1] += c * 2.0 * st.J43 * (st.I1 * ds.GF - ddot(Gw, st.FC) - (2.0 / 3.0) * st.I2 * ds.GFiT);
+                gt[2] += c * (st.J - 1.0) * st.J * ds.GFiT;
+            }
         }
         m3 Qm;
         to_parent(Fb, K, E::weight(q), Qm);
@@ -670,9 +794,9 @@ struct TileCsr {
 
 // LDS layout of a tile: the node records (later overwritten by the element
 // slots of one component), then the assembly tables.
-__device__ __forceinline__ TileCsr csr_layout(double *smem, int nl, int rec_len, int nen, int te)
+__device__ __forceinline__ TileCsr csr_layout(double *smem, int nl, int rec_len, int nen, int te, int nc)
 {
-    const int a = max(nl * rec_len, nen * te);   // doubles
+    const int a = max(nl * rec_len, nc * nen * te);   // doubles
     TileCsr c;
     c.ptr = reinterpret_cast<int32_t *>(smem + a);
     c.dst = c.ptr + nl + 1;
@@ -722,41 +846,78 @@ __device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, co
         if (tid + k * nthr < n_words) sw[tid + k * nthr] = wv[k];
 }
 
-// Sum, for every local node, its element slots (CSR order) of one component
-// and write the value to the output (node owned by this tile only) or to the
-// node's partial slot in row `row` of the partial buffer (shared node).
-__device__ __forceinline__ void reduce_component(const DevMesh &m, const TileDesc &t, const TileCsr &c,
-                                                 const double *__restrict__ slot, double *__restrict__ out,
-                                                 int row, int comp, int tid, int nthr)
+// Sum, for every local node, its element slots (CSR order) of the
+// components r0 .. r0 + NC - 1 (slot region of component r0 + k at
+// k * slot_stride) and write each value to the output (node owned by this
+// tile only) or to the node's partial slot (shared node, partial row
+// 3 * field + r).  The slot list is read eight entries at a time so that the
+// loads of a node are independent.
+template <int NC>
+__device__ __forceinline__ void reduce_components(const DevMesh &m, const TileDesc &t, const TileCsr &c,
+                                                  const double *__restrict__ slot, int slot_stride,
+                                                  double *__restrict__ out, int field, int r0, int tid, int nthr)
 {
+    constexpr int U = 8;
     for (int l = tid; l < t.n_node; l += nthr) {
         const int p0 = c.ptr[l], p1 = c.ptr[l + 1];
-        double s = 0.0;
-        for (int p = p0; p < p1; ++p) s += slot[c.slot[p]];
+        double s[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) s[k] = 0.0;
+        for (int p = p0; p < p1; p += U) {
+            int id[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) id[u] = p + u < p1 ? (int)c.slot[p + u] : -1;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (id[u] >= 0) {
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) s[k] += slot[k * slot_stride + id[u]];
+                }
+        }
         const int d = c.dst[l];
-        if (d >= 0) out[comp * m.n_nodes + d] = s;
-        else m.part[(int64_t)row * m.n_part + (-1 - d)] = s;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            if (d >= 0) out[(r0 + k) * m.n_nodes + d] = s[k];
+            else m.part[(int64_t)(3 * field + r0 + k) * m.n_part + (-1 - d)] = s[k];
+        }
     }
 }
 
-// Deterministic assembly of the element vectors of a tile, one component at
-// a time so that the LDS slots (a * te + i) need NEN x te doubles only; the
-// slots overwrite the node records, which are dead once every lane is done.
-template <int NEN>
-__device__ __forceinline__ void assemble(const DevMesh &m, const TileDesc &t, const TileCsr &c,
-                                         double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
-                                         double *__restrict__ out, int field, int tid, int te)
+// Deterministic assembly of the element vectors of a tile, NC components per
+// round (the host picks NC so that NC x NEN x te slot doubles fit the
+// workgroup's LDS); the slots a * te + i overwrite the node records, which
+// are dead once every lane is done.
+template <int NEN, int NC>
+__device__ __forceinline__ void assemble_nc(const DevMesh &m, const TileDesc &t, const TileCsr &c,
+                                            double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
+                                            double *__restrict__ out, int field, int tid, int te)
 {
+    const int stride = NEN * te;
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int r0 = 0; r0 < 3; r0 += NC) {
         __syncthreads();
         if (active) {
 #pragma unroll
-            for (int a = 0; a < NEN; ++a) sm[a * te + tid] = fe[a][r];
+            for (int k = 0; k < NC; ++k)
+                if (r0 + k < 3) {
+#pragma unroll
+                    for (int a = 0; a < NEN; ++a) sm[k * stride + a * te + tid] = fe[a][r0 + k];
+                }
         }
         __syncthreads();
-        reduce_component(m, t, c, sm, out, 3 * field + r, r, tid, te);
+        if (r0 + NC <= 3) reduce_components<NC>(m, t, c, sm, stride, out, field, r0, tid, te);
+        else reduce_components<(3 % NC) ? (3 % NC) : 1>(m, t, c, sm, stride, out, field, r0, tid, te);
     }
+}
+
+template <int NEN>
+__device__ __forceinline__ void assemble(const DevMesh &m, const TileDesc &t, const TileCsr &c,
+                                         double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
+                                         double *__restrict__ out, int field, int tid, int te, int nc)
+{
+    if (nc >= 3) assemble_nc<NEN, 3>(m, t, c, sm, fe, active, out, field, tid, te);
+    else if (nc == 2) assemble_nc<NEN, 2>(m, t, c, sm, fe, active, out, field, tid, te);
+    else assemble_nc<NEN, 1>(m, t, c, sm, fe, active, out, field, tid, te);
 }
 
 // Zeros for every destination of the tile's nodes (an undamped tile's share
@@ -779,7 +940,7 @@ __device__ __forceinline__ void zero_nodes(const DevMesh &m, const TileDesc &t, 
 #define TLFEA_MAX_TE 256
 
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LAW == 1 ? 2 : 3))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LAW == 1 ? 2 : 3))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpFwd, DAMPED>;
@@ -788,7 +949,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LA
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
-    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te);
+    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
     stage_csr<NEN>(csr, m, t, tid, te);
     stage_tile<kOpFwd, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
@@ -803,11 +964,11 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LA
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
         fwd_element<ELEM, LAW, DAMPED>(smem, na, mt, fe);
     }
-    assemble<NEN>(m, t, csr, smem, fe, active, c.out0, 0, tid, te);
+    assemble<NEN>(m, t, csr, smem, fe, active, c.out0, 0, tid, te, nc);
 }
 
-template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl)
+template <int ELEM, int LAW, bool DAMPED, bool WANT_GT>
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpVjp, DAMPED>;
@@ -816,7 +977,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2)
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
-    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te);
+    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
     stage_csr<NEN>(csr, m, t, tid, te);
     stage_tile<kOpVjp, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
@@ -831,8 +992,8 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2)
         load_na<NEN, R::len>(m, t, tid, te, na);
         const int uid = m.elem_uid[t.elem_begin + tid];
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
-        vjp_element<ELEM, LAW, DAMPED>(smem, na, mt, gx, gv, gt);
-        if (c.gtheta) {
+        vjp_element<ELEM, LAW, DAMPED, WANT_GT>(smem, na, mt, gx, gv, gt);
+        if (WANT_GT) {
             // rows a law does not use (and the viscous rows when undamped) are 0
             c.gtheta[uid] = gt[0];
             c.gtheta[m.n_elem + uid] = (LAW == 1 || LAW == 0) ? gt[1] : 0.0;
@@ -841,9 +1002,9 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2)
             c.gtheta[4 * m.n_elem + uid] = DAMPED ? gt[4] : 0.0;
         }
     }
-    if (c.out0) assemble<NEN>(m, t, csr, smem, gx, active, c.out0, 0, tid, te);
+    if (c.out0) assemble<NEN>(m, t, csr, smem, gx, active, c.out0, 0, tid, te, nc);
     if (c.out1) {
-        if constexpr (DAMPED) assemble<NEN>(m, t, csr, smem, gv, active, c.out1, 1, tid, te);
+        if constexpr (DAMPED) assemble<NEN>(m, t, csr, smem, gv, active, c.out1, 1, tid, te, nc);
         else zero_nodes(m, t, csr, c.out1, 1, tid, te);
     }
 }
@@ -851,7 +1012,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2)
 // The tangent stages dx (zeros when null) and, for damped blocks, dv (zeros
 // when null), so one instantiation serves every combination.
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl)
+__global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpJvp, DAMPED>;
@@ -860,7 +1021,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
-    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te);
+    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
     stage_csr<NEN>(csr, m, t, tid, te);
     stage_tile<kOpJvp, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
@@ -875,33 +1036,36 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
         jvp_element<ELEM, LAW, DAMPED>(smem, na, mt, df);
     }
-    assemble<NEN>(m, t, csr, smem, df, active, c.out0, 0, tid, te);
+    assemble<NEN>(m, t, csr, smem, df, active, c.out0, 0, tid, te, nc);
 }
 
 template <int OP, int ELEM, int LAW, bool DAMPED>
 hipError_t launch_one(dim3 grid, int te, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c, int tile0,
-                      int ntile, int nl)
+                      int ntile, int nl, int nc)
 {
-    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl);
-    else if constexpr (OP == kOpVjp) k_vjp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl);
-    else k_jvp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl);
+    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+    else if constexpr (OP == kOpVjp) {
+        if (c.gtheta) k_vjp<ELEM, LAW, DAMPED, true><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+        else k_vjp<ELEM, LAW, DAMPED, false><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+    }
+    else k_jvp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     return hipGetLastError();
 }
 
 template <int OP, int ELEM>
 hipError_t launch_class(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m,
-                        const CallArgs &c, int tile0, int nl)
+                        const CallArgs &c, int tile0, int nl, int nc)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
     switch (law * 2 + (damped ? 1 : 0)) {
-    case 0: return launch_one<OP, ELEM, 0, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
-    case 1: return launch_one<OP, ELEM, 0, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
-    case 2: return launch_one<OP, ELEM, 1, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
-    case 3: return launch_one<OP, ELEM, 1, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
-    case 4: return launch_one<OP, ELEM, 2, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
-    case 5: return launch_one<OP, ELEM, 2, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl);
+    case 0: return launch_one<OP, ELEM, 0, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 1: return launch_one<OP, ELEM, 0, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 2: return launch_one<OP, ELEM, 1, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 3: return launch_one<OP, ELEM, 1, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 4: return launch_one<OP, ELEM, 2, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 5: return launch_one<OP, ELEM, 2, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
     default: return hipErrorInvalidValue;
     }
 }

@@ -21,7 +21,7 @@
 namespace tlfea {
 #define TLFEA_DECL(e, o)                                                                                   \
     hipError_t launch_tiles_e##e##_o##o(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, \
-                                        const DevMesh &m, const CallArgs &c, int tile0, int nl);
+                                        const DevMesh &m, const CallArgs &c, int tile0, int nl, int nc);
 TLFEA_DECL(0, 0)
 TLFEA_DECL(0, 1)
 TLFEA_DECL(0, 2)
@@ -32,13 +32,14 @@ TLFEA_DECL(1, 2)
 hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1);
 
 static hipError_t launch_tiles(int elem, int law, int damped, int te, int op, int n_tiles, size_t lds, hipStream_t s,
-                               const DevMesh &m, const CallArgs &c, int tile0, int nl)
+                               const DevMesh &m, const CallArgs &c, int tile0, int nl, int nc)
 {
-    typedef hipError_t (*fn_t)(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int);
+    typedef hipError_t (*fn_t)(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int,
+                               int);
     static const fn_t table[2][3] = {{launch_tiles_e0_o0, launch_tiles_e0_o1, launch_tiles_e0_o2},
                                      {launch_tiles_e1_o0, launch_tiles_e1_o1, launch_tiles_e1_o2}};
     if (elem < 0 || elem > 1 || op < 0 || op > 2) return hipErrorInvalidValue;
-    return table[elem][op](law, damped, te, n_tiles, lds, s, m, c, tile0, nl);
+    return table[elem][op](law, damped, te, n_tiles, lds, s, m, c, tile0, nl, nc);
 }
 }  // namespace tlfea
 
@@ -85,6 +86,7 @@ struct ClassRange {
     int elem, law, damped, te;
     int tile_begin, tile_count;
     int nl_cap;          // most distinct nodes of a tile of the class (LDS records to allocate)
+    int nc[3];           // components assembled per round, per operation
 };
 
 struct GraphEntry {
@@ -237,23 +239,46 @@ struct HostBuild {
 static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
 
 // Distinct nodes a tile may hold: at most kStagePerThread per thread, and
-// few enough that every operation's LDS (node records plus assembly tables,
-// see lds_bytes) stays within its budget: the device's per-workgroup limit,
-// and at most the share of a 160 KiB compute-unit LDS that lets the
+// few enough that every operation's node records and assembly tables stay
+// within its LDS budget.
+// LDS budget of one workgroup of an operation: the device's per-workgroup
+// limit, and at most the share of a 160 KiB compute-unit LDS that lets the
 // workgroups the kernel's register use allows (three for the forward, two
 // for the adjoint and the tangent) be resident together.
+static int64_t lds_budget(int op, int64_t lds_dev)
+{
+    static const int wgs[3] = {3, 2, 2};
+    return std::min<int64_t>(lds_dev, 163840 / wgs[op]);
+}
+
 static int nl_limit(int elem, int te, int damped, int64_t lds_dev)
 {
     const int nen = nen_of(elem);
     int64_t nl = (int64_t)kStagePerThread * te;
-    const int wgs[3] = {3, 2, 2};
     for (int op = kOpFwd; op <= kOpJvp; ++op) {
-        const int64_t budget = std::min<int64_t>(lds_dev, 163840 / wgs[op]);
         const int64_t fixed = 4 + (int64_t)nen * te * 2;
         const int64_t per_node = 8 * (int64_t)record_len(op, damped != 0) + 8;
-        nl = std::min(nl, (budget - fixed) / per_node);
+        nl = std::min(nl, (lds_budget(op, lds_dev) - fixed) / per_node);
     }
     return (int)nl;
+}
+
+// LDS of one workgroup: the node records (reused for the element slots of
+// nc components), then the tile's assembly tables (see the kernels).
+static size_t lds_bytes(const ClassRange &c, int op, int nc)
+{
+    const size_t records = (size_t)c.nl_cap * record_len(op, c.damped != 0);
+    const size_t slots = (size_t)nc * nen_of(c.elem) * c.te;
+    const size_t tables = (size_t)(2 * c.nl_cap + 1) * sizeof(int32_t) + (size_t)nen_of(c.elem) * c.te * sizeof(uint16_t);
+    return std::max(records, slots) * sizeof(double) + tables;
+}
+
+// Components assembled per round: as many as fit the operation's budget.
+static int comps_per_round(const ClassRange &c, int op, int64_t lds_dev)
+{
+    for (int nc = 3; nc > 1; --nc)
+        if ((int64_t)lds_bytes(c, op, nc) <= lds_budget(op, lds_dev)) return nc;
+    return 1;
 }
 
 // Cut the elements `ids` (one block, Morton order) into tiles of at most te
@@ -382,7 +407,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
     std::vector<std::vector<int64_t>> groups;
     int64_t elem_cursor = 0;
     for (size_t k = 0; k < keys.size(); ++k) {
-        ClassRange cr{keys[k].elem, keys[k].law, keys[k].damped, keys[k].te, (int)hb.tiles.size(), 0, 0};
+        ClassRange cr{keys[k].elem, keys[k].law, keys[k].damped, keys[k].te, (int)hb.tiles.size(), 0, 0, {1, 1, 1}};
         const int te = keys[k].te, nen = nen_of(keys[k].elem);
         const int nlmax = nl_limit(keys[k].elem, te, keys[k].damped, lds_dev);
         if (nlmax < nen || (int64_t)nen * te * (int64_t)sizeof(double) > 65536)
@@ -478,6 +503,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
             }
         }
         cr.tile_count = (int)hb.tiles.size() - cr.tile_begin;
+        for (int op = kOpFwd; op <= kOpJvp; ++op) cr.nc[op] = comps_per_round(cr, op, lds_dev);
         if (cr.tile_count > 0) hb.classes.push_back(cr);
     }
     if (hb.lnode_slot.size() & 1) hb.lnode_slot.push_back(0);   // whole 32-bit words
@@ -633,21 +659,11 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
 
 // ------------------------------------------------------------------ launching
 
-// LDS of one workgroup: the node records (reused for the element slots of
-// one component), then the tile's assembly tables (see the kernels).
-static size_t lds_bytes(const ClassRange &c, int op)
-{
-    const size_t records = (size_t)c.nl_cap * record_len(op, c.damped != 0);
-    const size_t slots = (size_t)nen_of(c.elem) * c.te;
-    const size_t tables = (size_t)(2 * c.nl_cap + 1) * sizeof(int32_t) + (size_t)nen_of(c.elem) * c.te * sizeof(uint16_t);
-    return std::max(records, slots) * sizeof(double) + tables;
-}
-
 static tlfea_status enqueue(tlfea_mesh *m, int op, const CallArgs &c, hipStream_t s, bool timed)
 {
     const int kid = op;   // kernel id: 0 fwd, 1 vjp, 2 jvp
     for (const ClassRange &cr : m->classes) {
-        const size_t lds = lds_bytes(cr, op);
+        const size_t lds = lds_bytes(cr, op, cr.nc[op]);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timed) {
             HIP_TRY(hipEventCreate(&e0));
@@ -655,7 +671,7 @@ static tlfea_status enqueue(tlfea_mesh *m, int op, const CallArgs &c, hipStream_
             HIP_TRY(hipEventRecord(e0, s));
         }
         hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, s, m->dm, c,
-                                    cr.tile_begin, cr.nl_cap);
+                                    cr.tile_begin, cr.nl_cap, cr.nc[op]);
         if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "tile kernel launch: %s", hipGetErrorString(e));
         if (timed) {
             HIP_TRY(hipEventRecord(e1, s));
@@ -804,12 +820,12 @@ static tlfea_status time_classes(tlfea_mesh *m, std::vector<double> &t_cls)
         for (int op = kOpFwd; op <= kOpVjp; ++op) {
             CallArgs c{};
             c.x = x; c.v = v; c.w = w; c.out0 = o0; c.out1 = o1;
-            const size_t lds = lds_bytes(cr, op);
+            const size_t lds = lds_bytes(cr, op, cr.nc[op]);
             float best = 1e30f;
             for (int rep = 0; rep < 4; ++rep) {
                 HIP_TRY(hipEventRecord(e0, nullptr));
                 hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, nullptr, m->dm,
-                                            c, cr.tile_begin, cr.nl_cap);
+                                            c, cr.tile_begin, cr.nl_cap, cr.nc[op]);
                 if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "autotune launch: %s", hipGetErrorString(e));
                 HIP_TRY(hipEventRecord(e1, nullptr));
                 HIP_TRY(hipEventSynchronize(e1));

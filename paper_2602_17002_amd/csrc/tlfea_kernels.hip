@@ -17,9 +17,9 @@ namespace tlfea {
 
 hipError_t TLFEA_CAT(launch_tiles, TLFEA_ELEM, TLFEA_OP)(int law, int damped, int te, int n_tiles, size_t lds,
                                                           hipStream_t s, const DevMesh &m, const CallArgs &c,
-                                                          int tile0, int nl)
+                                                          int tile0, int nl, int nc)
 {
-    return launch_class<TLFEA_OP, TLFEA_ELEM>(law, damped, te, n_tiles, lds, s, m, c, tile0, nl);
+    return launch_class<TLFEA_OP, TLFEA_ELEM>(law, damped, te, n_tiles, lds, s, m, c, tile0, nl, nc);
 }
 
 #if TLFEA_ELEM == 0 && TLFEA_OP == 0
