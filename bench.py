@@ -233,6 +233,81 @@ def batched_vs_plain(steps, warmup):
             "bitwise_equal_per_body": bool(same)}
 
 
+def batched_c5(steps, warmup):
+    """Forward, adjoint (gx, gtheta) and tangent of a 256-body multibody set:
+    one autotuned batched mesh whose three calls are captured into one graph,
+    against one plain mesh per body with the three calls launched eagerly."""
+    import copy
+
+    import torch
+
+    import synth
+    from paper_2602_17002_amd import AUTOTUNE, BATCHED, Mesh
+    t0 = time.time()
+    p = synth.config_c5()
+    log(f"[bench] C5: {len(p.blocks)} bodies, {p.n_elem} elements ({time.time() - t0:.1f} s)")
+    dev = torch.device("cuda", 0)
+    s = torch.cuda.Stream(device=dev)
+    t0 = time.time()
+    batched = Mesh(p.X, [copy.copy(b) for b in p.blocks], flags=BATCHED | AUTOTUNE)
+    tuned = batched.info()
+    log(f"[bench] C5 batched mesh autotuned in {time.time() - t0:.1f} s: {tuned}")
+    plains, col = [], 0
+    for bi, b in enumerate(p.blocks):
+        n0, n1 = p.body_nodes[bi]
+        bb = copy.copy(b)
+        bb.conn = b.conn - n0
+        plains.append((Mesh(p.X[:, n0:n1], [bb]), n0, n1, col, col + b.n_elem))
+        col += b.n_elem
+    with torch.cuda.stream(s):
+        x, w, dx = (torch.from_numpy(a).to(dev) for a in (p.x, p.w, p.dx))
+        f, gx, df = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+        gt = torch.empty((5, p.n_elem), dtype=torch.float64, device=dev)
+        g = torch.cuda.CUDAGraph()
+        batched.internal_force(x, out=f)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            batched.internal_force(x, out=f)
+            batched.vjp(x, None, w, want_v=False, out=(gx, None, gt))
+            batched.jvp(x, None, dx, out=df)
+        per = []
+        for m, n0, n1, c0, c1 in plains:
+            xs, ws, ds = x[:, n0:n1].contiguous(), w[:, n0:n1].contiguous(), dx[:, n0:n1].contiguous()
+            per.append((m, xs, ws, ds, torch.empty_like(xs), torch.empty_like(xs), torch.empty_like(xs),
+                        torch.empty((5, c1 - c0), dtype=torch.float64, device=dev)))
+
+        def run_plain():
+            for m, xs, ws, ds, ff, gg, dd, tt in per:
+                m.internal_force(xs, out=ff)
+                m.vjp(xs, None, ws, want_v=False, out=(gg, None, tt))
+                m.jvp(xs, None, ds, out=dd)
+
+        res = {}
+        for name, fn in (("batched", g.replay), ("plain", run_plain)):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(steps):
+                fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            res[name] = e0.elapsed_time(e1) / steps
+        # the tuned tile sizes differ from the plain meshes' default, so the
+        # summation order (not the arithmetic) differs: compare norm-wise
+        def nrel(a, b):
+            return float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+        diff = max(max(nrel(f[:, n0:n1], ff), nrel(gx[:, n0:n1], gg), nrel(df[:, n0:n1], dd), nrel(gt[:, c0:c1], tt))
+                   for (_, n0, n1, c0, c1), (_, _, _, _, ff, gg, dd, tt) in zip(plains, per))
+    return {"workload": f"C5: {len(p.blocks)} bodies of 1,000-100,000 elements, mixed T10/H8, SVK/NH, "
+                        f"{p.n_elem} elements, forward + adjoint (gx, gtheta) + tangent in one graph",
+            "tile_elems_t10": tuned["tile_elems_t10"], "tile_elems_h8": tuned["tile_elems_h8"],
+            "ms_batched": round(res["batched"], 4), "ms_plain": round(res["plain"], 4),
+            "speedup": round(res["plain"] / res["batched"], 3), "max_rel_diff_per_body": diff}
+
+
 # ---------------------------------------------------------------- profiler summaries
 
 def _csv_rows(pattern):
@@ -303,6 +378,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-body batched vs plain comparison")
+    ap.add_argument("--c5", action="store_true", help="also time the 256-body forward + adjoint + tangent graph")
     ap.add_argument("--tile", type=int, default=0, help="elements per tile (0 = library default)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of known "
@@ -410,6 +486,8 @@ def main():
     }
     if not args.no_batched:
         out["batched_vs_plain"] = batched_vs_plain(max(3, args.steps // 4), 2)
+    if args.c5:
+        out["batched_c5"] = batched_c5(max(3, args.steps // 4), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

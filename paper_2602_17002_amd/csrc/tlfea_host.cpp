@@ -702,6 +702,14 @@ static tlfea_status run(tlfea_mesh *m, int op, const CallArgs &c, void *stream)
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != m->device) return fail(TLFEA_E_INVALID, "current device %d differs from the mesh's device %d", dev, m->device);
+    // A stream the caller is capturing gets the launches themselves (the
+    // caller's graph then holds them, e.g. forward, adjoint and tangent in
+    // one graph); kernel timing is off inside a capture.
+    if (s != nullptr) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(s, &cs));
+        if (cs != hipStreamCaptureStatusNone) return enqueue(m, op, c, s, false);
+    }
     // graphs cannot be captured on the null stream: launch directly there
     if (!(m->flags & TLFEA_BATCHED) || s == nullptr) return enqueue(m, op, c, s, m->prof);
     // batched: one hipGraph per (op, operand pointers, stream), replayed
@@ -855,10 +863,10 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
     // Autotune: per (element, law, damping) class, the tile size with the
     // smallest forward + adjoint time over the class's own tiles; blocks that
     // fix tile_elems keep it.
-    const int cand[3] = {64, 128, 256};
+    const int cand[4] = {64, 128, 192, 256};
     std::vector<double> best_t(n_blocks, 1e300);
     std::vector<int> best_te = te;
-    for (int ci = 0; ci < 3; ++ci) {
+    for (int ci = 0; ci < 4; ++ci) {
         std::vector<int> tc(n_blocks);
         for (int b = 0; b < n_blocks; ++b) tc[b] = blocks[b].tile_elems ? blocks[b].tile_elems : cand[ci];
         tlfea_mesh *m = nullptr;

@@ -316,3 +316,81 @@ def test_full_size_sampled_against_oracle(cfg):
             e = rel(a, b)
             say(cfg, k, "rel", e)
             assert e <= TOL, (k, e)
+
+
+def test_c4_finite_differences_and_adjoint_consistency():
+    """The 204,000-element Neo-Hookean body with per-element (mu, lambda):
+    the tangent against central differences of the GPU forward (h = 1e-6
+    relative), the parameter gradient against exact differences (f is linear
+    in the parameters), and w . (K dx) = gx . dx."""
+    import torch
+    p = synth.config_c4()
+    say("C4 finite differences", p.n_elem)
+    m = mesh_of(p)
+    x, w, dx = to_dev(p.x), to_dev(p.w), to_dev(p.dx)
+    th = to_dev(p.theta_all())
+    gx, _, gt = m.vjp(x, None, w, th, want_v=False)
+    kdx = m.jvp(x, None, dx, None, th)
+    h = 1e-6
+    fd = (m.internal_force(x + h * dx, None, th) - m.internal_force(x - h * dx, None, th)) / (2 * h)
+    e_fd = float((fd - kdx).abs().max() / kdx.abs().max())
+    say("C4 K.dx vs central differences", e_fd)
+    assert e_fd <= 1e-7
+    a, b = float((w * kdx).sum()), float((gx * dx).sum())
+    say("C4 w.(K dx) vs gx.dx", abs(a - b) / abs(b))
+    assert abs(a - b) <= 1e-12 * float((w.abs() * kdx.abs()).sum())
+    d = torch.from_numpy(np.random.default_rng(21).standard_normal(th.shape) * 0.01).to("cuda") * th
+    e1 = float((w * m.internal_force(x, None, th + d)).sum())
+    e0 = float((w * m.internal_force(x, None, th - d)).sum())
+    lin = float((gt * d).sum())
+    say("C4 gtheta vs exact differences", abs((e1 - e0) / 2 - lin) / abs(lin))
+    assert abs((e1 - e0) / 2 - lin) <= 1e-10 * abs(lin)
+    torch.cuda.synchronize()
+
+
+def test_one_graph_forward_adjoint_tangent_autotuned_batch():
+    """Forward, adjoint and tangent of an autotuned multibody batch captured
+    by the caller into one graph; every replay (with eager work between
+    replays) equals the eager calls bitwise and the oracle within the bound."""
+    import torch
+    from paper_2602_17002_amd import AUTOTUNE, BATCHED
+    p = synth.config_multibody(10, 300, 4000, seed=31, directions=True)
+    say("one graph", len(p.blocks), p.n_elem)
+    m = mesh_of(p, flags=BATCHED | AUTOTUNE)
+    info = m.info()
+    assert info["tile_elems_t10"] in (64, 128, 192, 256) and info["tile_elems_h8"] in (64, 128, 192, 256)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        x, w, dx = to_dev(p.x), to_dev(p.w), to_dev(p.dx)
+        f, gx, df = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+        gt = torch.empty((5, p.n_elem), dtype=torch.float64, device="cuda")
+        m.internal_force(x, out=f)
+        m.vjp(x, None, w, want_v=False, out=(gx, None, gt))
+        m.jvp(x, None, dx, out=df)
+        torch.cuda.synchronize()
+        ref = [t.clone() for t in (f, gx, gt, df)]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            m.internal_force(x, out=f)
+            m.vjp(x, None, w, want_v=False, out=(gx, None, gt))
+            m.jvp(x, None, dx, out=df)
+        for rep in range(3):
+            for t in (f, gx, gt, df):
+                t.fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for a, b in zip((f, gx, gt, df), ref):
+                assert torch.equal(a, b), rep
+            # eager work between replays
+            m.internal_force(x + 0.0, out=torch.empty_like(x))
+            torch.cuda.synchronize()
+    Xc, xc = centred(p.X, p.x, p.body_nodes)
+    assert rel(to_host(f), O.internal_force(Xc, p.blocks, xc)) <= TOL
+    rx, _, rt = O.vjp(Xc, p.blocks, xc, None, p.w, want_gv=False)
+    assert rel(to_host(gx), rx) <= TOL
+    gth = to_host(gt)
+    for r in (0, 1, 2):
+        if np.abs(rt[r]).max() > 0:
+            assert rel(gth[r], rt[r]) <= TOL
+    assert rel(to_host(df), O.jvp(Xc, p.blocks, xc, None, p.dx)) <= TOL
