@@ -379,6 +379,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-body batched vs plain comparison")
     ap.add_argument("--c5", action="store_true", help="also time the 256-body forward + adjoint + tangent graph")
+    ap.add_argument("--keep-node-order", action="store_true",
+                    help="keep the generator's node numbering instead of the library's suggested order")
     ap.add_argument("--tile", type=int, default=0, help="elements per tile (0 = library default)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of known "
@@ -406,6 +408,11 @@ def main():
     torch.cuda.set_device(dev)
     t0 = time.time()
     mesh = Mesh.from_problem(prob, tile_elems=args.tile or None)
+    if not args.keep_node_order:
+        # renumber the nodes once, as the library suggests (tile nodes contiguous)
+        prob = prob.renumbered(mesh.node_order())
+        mesh.close()
+        mesh = Mesh.from_problem(prob, tile_elems=args.tile or None)
     info = mesh.info()
     log(f"[bench] mesh built in {time.time() - t0:.1f} s: {info}")
     stream = torch.cuda.Stream(device=dev)

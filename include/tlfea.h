@@ -154,6 +154,17 @@ tlfea_status tlfea_tangent_jvp(tlfea_mesh *mesh, const double *x, const double *
                                const double *theta, const double *dx, const double *dv,
                                double *df, void *stream);
 
+/*
+ * A node numbering under which the nodes of every tile are (nearly)
+ * contiguous: order[k] is the caller's node that should become node k
+ * (HOST int32[n_nodes], written).  The mesh is unchanged.  Renumbering X,
+ * the connectivity and every nodal array once with it, and creating the
+ * mesh again from the renumbered data, makes the kernels' node gathers and
+ * stores coalesced; results are the same up to the renumbering (the tiles
+ * and their summation order do not depend on node numbers).
+ */
+tlfea_status tlfea_node_order(const tlfea_mesh *mesh, int32_t *order);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *tlfea_last_error(void);
 

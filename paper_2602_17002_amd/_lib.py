@@ -21,7 +21,7 @@ KERNEL_IDS = ("forward_tile", "adjoint_tile", "tangent_tile", "halo", "batched_g
 
 EXPORTS = ("tlfea_create_mesh", "tlfea_destroy_mesh", "tlfea_get_mesh_info", "tlfea_internal_force",
            "tlfea_internal_force_vjp", "tlfea_tangent_jvp", "tlfea_last_error", "tlfea_set_profiling",
-           "tlfea_get_profile", "tlfea_reset_profile")
+           "tlfea_get_profile", "tlfea_reset_profile", "tlfea_node_order")
 
 
 class Block(C.Structure):
@@ -77,6 +77,8 @@ def lib():
     L.tlfea_get_profile.restype = C.c_int
     L.tlfea_reset_profile.argtypes = [vp]
     L.tlfea_reset_profile.restype = C.c_int
+    L.tlfea_node_order.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.tlfea_node_order.restype = C.c_int
     _lib = L
     return L
 

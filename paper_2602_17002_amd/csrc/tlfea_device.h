@@ -718,13 +718,13 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return t < n ? t : -1;
 }
 
-// Global source of field f of the LDS node record (record order X, x, then
-// w or dx, then v, then dv); null operands (dx or dv of the tangent) read as 0.
+// Global source of field f of the LDS node record (record order x, then w
+// or dx, then v, then dv; X comes from the mesh's tile records); null
+// operands (dx or dv of the tangent) read as 0.
 template <int OP, bool DAMPED>
-__device__ __forceinline__ const double *field_src(int f, const DevMesh &m, const CallArgs &c)
+__device__ __forceinline__ const double *field_src(int f, const CallArgs &c)
 {
     using R = Rec<OP, DAMPED>;
-    if (f == R::oX / 3) return m.X;
     if (f == R::ox / 3) return c.x;
     if (R::has2 && f == R::o2 / 3) return OP == kOpVjp ? c.w : c.dx;
     if (DAMPED && f == R::ov / 3) return c.v;
@@ -737,7 +737,9 @@ __device__ __forceinline__ const double *field_src(int f, const DevMesh &m, cons
 // node: the kinematics only use differences of nodal positions (the parent
 // gradients of an element sum to zero), and coordinates of the size of a
 // tile instead of the size of the body keep the per-point gradient sums free
-// of cancellation.
+// of cancellation.  The reference part is read contiguously from the mesh,
+// which stores it per tile node already relative to the tile's first node;
+// the other fields are gathered from the caller's [3][n] arrays.
 template <int OP, bool DAMPED>
 __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMesh &m, const CallArgs &c,
                                            const TileDesc &t, int tid, int nthr)
@@ -755,9 +757,15 @@ __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMes
     }
     double v[kStagePerThread][3 * R::nfield];
 #pragma unroll
-    for (int f = 0; f < nf; ++f) {
-        const double *p = field_src<OP, DAMPED>(f, m, c);
-        const bool centre = f == R::oX / 3 || f == R::ox / 3;
+    for (int cc = 0; cc < 3; ++cc) {
+        const double *xt = m.Xt + cc * m.n_tnode + t.node_begin;
+#pragma unroll
+        for (int k = 0; k < kStagePerThread; ++k) v[k][R::oX + cc] = g[k] >= 0 ? xt[tid + k * nthr] : 0.0;
+    }
+#pragma unroll
+    for (int f = 1; f < nf; ++f) {
+        const double *p = field_src<OP, DAMPED>(f, c);
+        const bool centre = f == R::ox / 3;
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
             const double o = centre ? p[cc * n + g0] : 0.0;

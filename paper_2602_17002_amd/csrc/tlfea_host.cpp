@@ -109,6 +109,7 @@ struct tlfea_mesh {
     std::vector<void *> allocations;
     int64_t device_bytes = 0;
     int64_t n_tiles = 0;
+    std::vector<int32_t> tile_nodes;   // global node of every tile node, tile order (host copy)
     // profiling
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[5];
@@ -613,9 +614,21 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
         if (blocks[b].elem == kH8 && !m->te_h8) m->te_h8 = te_of_block[b];
     }
     m->classes = hb.classes;
+    m->tile_nodes = hb.lnode_gid;
     m->n_tiles = (int64_t)hb.tiles.size();
     DevMesh &d = m->dm;
-    std::vector<double> Xv(X, X + 3 * n_nodes);
+    // reference coordinates per tile node, relative to the tile's first node
+    // (the same differences the kernels would form from X)
+    const int64_t n_tnode = (int64_t)hb.lnode_gid.size();
+    std::vector<double> Xt(3 * (size_t)n_tnode);
+    for (const TileDesc &t : hb.tiles) {
+        const int32_t g0 = hb.lnode_gid[t.node_begin];
+        for (int l = 0; l < t.n_node; ++l) {
+            const int32_t g = hb.lnode_gid[t.node_begin + l];
+            for (int c = 0; c < 3; ++c)
+                Xt[c * n_tnode + t.node_begin + l] = X[c * n_nodes + g] - X[c * n_nodes + g0];
+        }
+    }
     std::vector<double> part_dummy;
 #define UP(vec, ptr)                                                                                       \
     do {                                                                                                   \
@@ -632,7 +645,7 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
     UP(hb.lnode_slot, d.lnode_slot);
     UP(hb.elem_uid, d.elem_uid);
     UP(m->blocks, d.blocks);
-    UP(Xv, d.X);
+    UP(Xt, d.Xt);
     UP(hb.halo_gid, d.halo_gid);
     UP(hb.halo_ptr, d.halo_ptr);
 #undef UP
@@ -640,6 +653,7 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
     d.n_elem = m->n_elem;
     d.n_part = hb.n_part;
     d.n_halo = (int64_t)hb.halo_gid.size();
+    d.n_tnode = n_tnode;
     d.part = nullptr;
     if (hb.n_part > 0) {
         void *p = nullptr;
@@ -807,7 +821,7 @@ extern "C" tlfea_status tlfea_tangent_jvp(tlfea_mesh *m, const double *x, const 
 // ------------------------------------------------------------------ autotune
 
 // Time forward + adjoint per class for one candidate tile size.
-static tlfea_status time_classes(tlfea_mesh *m, std::vector<double> &t_cls)
+static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vector<double> &t_cls)
 {
     const size_t nb = sizeof(double) * 3 * (size_t)m->n_nodes;
     double *x = nullptr, *v = nullptr, *w = nullptr, *o0 = nullptr, *o1 = nullptr;
@@ -816,7 +830,7 @@ static tlfea_status time_classes(tlfea_mesh *m, std::vector<double> &t_cls)
     HIP_TRY(hipMalloc(&w, nb));
     HIP_TRY(hipMalloc(&o0, nb));
     HIP_TRY(hipMalloc(&o1, nb));
-    HIP_TRY(hipMemcpy(x, m->dm.X, nb, hipMemcpyDeviceToDevice));
+    HIP_TRY(hipMemcpy(x, X_host, nb, hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(v, 0, nb));
     HIP_TRY(hipMemset(w, 0, nb));
     hipEvent_t e0, e1;
@@ -873,7 +887,7 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
         st = create_with(n_nodes, X, n_blocks, blocks, flags & ~TLFEA_BATCHED, tc, &m);
         if (st) return st;
         std::vector<double> t;
-        st = time_classes(m, t);
+        st = time_classes(m, X, t);
         if (st) {
             tlfea_destroy_mesh(m);
             return st;
@@ -960,5 +974,24 @@ extern "C" tlfea_status tlfea_reset_profile(tlfea_mesh *m)
         m->counts[k] = 0;
         m->ms[k] = 0;
     }
+    return TLFEA_OK;
+}
+
+// ------------------------------------------------------------------ node order
+
+extern "C" tlfea_status tlfea_node_order(const tlfea_mesh *m, int32_t *order)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (!order && m->n_nodes > 0) return fail(TLFEA_E_INVALID, "order is NULL");
+    std::vector<char> seen(m->n_nodes, 0);
+    int64_t k = 0;
+    for (int32_t g : m->tile_nodes)
+        if (!seen[g]) {
+            seen[g] = 1;
+            order[k++] = g;
+        }
+    for (int64_t g = 0; g < m->n_nodes; ++g)
+        if (!seen[g]) order[k++] = (int32_t)g;
     return TLFEA_OK;
 }

@@ -37,11 +37,12 @@ struct DevMesh {
     const uint16_t *lnode_slot;   // element-force slot = a * te + i
     const int32_t *elem_uid;      // caller's element id of each internal element
     const BlockDesc *blocks;
-    const double *X;              // [3][n_nodes]
+    const double *Xt;             // [3][n_tnode] reference coordinates of every tile node,
+                                  // relative to its tile's first node
     const int32_t *halo_gid;      // nodes summed from partials (and nodes no element touches)
     const int32_t *halo_ptr;      // [n_halo + 1]: node h owns partial slots [halo_ptr[h], halo_ptr[h+1])
     double *part;                 // [6][n_part] partial node sums (two fields x three components)
-    int64_t n_nodes, n_elem, n_part, n_halo;
+    int64_t n_nodes, n_elem, n_part, n_halo, n_tnode;
 };
 
 // Per-call operands (device pointers; unused ones are null).

@@ -93,6 +93,13 @@ class Mesh:
         check(_lib.lib().tlfea_get_mesh_info(self.handle, C.byref(inf)), "tlfea_get_mesh_info")
         return {k: getattr(inf, k) for k, _ in MeshInfo._fields_}
 
+    def node_order(self):
+        """tlfea_node_order: order[k] = the node that should become node k."""
+        order = np.empty(self.n_nodes, dtype=np.int32)
+        check(_lib.lib().tlfea_node_order(self.handle, order.ctypes.data_as(C.POINTER(C.c_int32))),
+              "tlfea_node_order")
+        return order
+
     # ------------------------------------------------------------ checks
     def _nodal(self, t, name, required=True):
         if t is None:

@@ -218,6 +218,26 @@ class Problem:
     def n_qp(self):
         return sum(b.n_qp for b in self.blocks)
 
+    def renumbered(self, order):
+        """The same problem with node k of the result = node order[k] of this
+        one (X, connectivity and every nodal array permuted)."""
+        import copy as _copy
+        order = np.asarray(order, dtype=np.int64)
+        inv = np.empty_like(order)
+        inv[order] = np.arange(order.size)
+        p = _copy.copy(self)
+        for name in ("X", "x", "v", "w", "dx", "dv"):
+            a = getattr(self, name)
+            if a is not None:
+                setattr(p, name, np.ascontiguousarray(a[:, order]))
+        p.blocks = []
+        for b in self.blocks:
+            nb = _copy.copy(b)
+            nb.conn = np.ascontiguousarray(inv[b.conn].astype(np.int32))
+            p.blocks.append(nb)
+        p.body_nodes = None
+        return p
+
     def theta_all(self):
         """Per-element parameters [5][n_elem] over the concatenated blocks."""
         cols = []
