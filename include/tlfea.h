@@ -174,9 +174,11 @@ const char *tlfea_last_error(void);
  * synchronises those events and returns, per kernel id, the number of
  * launches and their summed duration in milliseconds; reset clears them.
  * Kernel ids: 0 forward tile, 1 adjoint tile, 2 tangent tile, 3 halo
- * reduction, 4 whole batched graph replay.  ids: HOST int32[5] counts,
- * ms: HOST double[5].
+ * reduction, 4 whole batched graph replay.  counts: HOST
+ * int32[TLFEA_NUM_KERNEL_IDS], ms: HOST double[TLFEA_NUM_KERNEL_IDS]; either
+ * may be NULL.
  */
+#define TLFEA_NUM_KERNEL_IDS 5
 tlfea_status tlfea_set_profiling(tlfea_mesh *mesh, int32_t enable);
 tlfea_status tlfea_get_profile(tlfea_mesh *mesh, int32_t *counts, double *ms);
 tlfea_status tlfea_reset_profile(tlfea_mesh *mesh);

@@ -97,6 +97,8 @@ struct GraphEntry {
     uint64_t stamp;
 };
 
+constexpr int kNumKernelIds = TLFEA_NUM_KERNEL_IDS;
+
 struct tlfea_mesh {
     int device = 0;
     int flags = 0;
@@ -112,9 +114,9 @@ struct tlfea_mesh {
     std::vector<int32_t> tile_nodes;   // global node of every tile node, tile order (host copy)
     // profiling
     bool prof = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[5];
-    int32_t counts[5] = {0, 0, 0, 0, 0};
-    double ms[5] = {0, 0, 0, 0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kNumKernelIds];
+    int32_t counts[kNumKernelIds] = {};
+    double ms[kNumKernelIds] = {};
     // graph cache
     std::vector<GraphEntry> graphs;
     uint64_t stamp = 0;
@@ -127,7 +129,7 @@ static void free_mesh_memory(tlfea_mesh *m)
     m->allocations.clear();
     for (auto &g : m->graphs) hipGraphExecDestroy(g.exec);
     m->graphs.clear();
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < kNumKernelIds; ++k) {
         for (auto &e : m->pending[k]) {
             hipEventDestroy(e.first);
             hipEventDestroy(e.second);
@@ -949,7 +951,7 @@ extern "C" tlfea_status tlfea_get_profile(tlfea_mesh *m, int32_t *counts, double
 {
     tlfea_status st = check_mesh(m);
     if (st) return st;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < kNumKernelIds; ++k) {
         for (auto &e : m->pending[k]) {
             HIP_TRY(hipEventSynchronize(e.second));
             float t = 0;
@@ -970,7 +972,7 @@ extern "C" tlfea_status tlfea_reset_profile(tlfea_mesh *m)
 {
     tlfea_status st = tlfea_get_profile(m, nullptr, nullptr);
     if (st) return st;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < kNumKernelIds; ++k) {
         m->counts[k] = 0;
         m->ms[k] = 0;
     }

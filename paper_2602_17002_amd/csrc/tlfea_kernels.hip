@@ -25,7 +25,8 @@ hipError_t TLFEA_CAT(launch_tiles, TLFEA_ELEM, TLFEA_OP)(int law, int damped, in
 #if TLFEA_ELEM == 0 && TLFEA_OP == 0
 // Nodes shared between tiles (and nodes no element touches): sum the node's
 // partial slots, which are contiguous and in tile order.  One lane per node;
-// up to two output fields.
+// up to two output fields.  Partials are read eight at a time (every load of
+// a lane in flight together); the sum still runs in tile order.
 __global__ __launch_bounds__(256) void k_halo(DevMesh m, double *out0, double *out1)
 {
     const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -33,17 +34,28 @@ __global__ __launch_bounds__(256) void k_halo(DevMesh m, double *out0, double *o
     const int g = m.halo_gid[h];
     const int p0 = m.halo_ptr[h], p1 = m.halo_ptr[h + 1];
     double *outs[2] = {out0, out1};
+    constexpr int U = 8;
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
         double *out = outs[f];
         if (!out) continue;
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int p = p0; p < p1; p += U) {
+            double v[3][U];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const double *part = m.part + (int64_t)(3 * f + r) * m.n_part;
-            double s = 0.0;
-            for (int p = p0; p < p1; ++p) s += part[p];
-            out[r * m.n_nodes + g] = s;
+            for (int r = 0; r < 3; ++r) {
+                const double *part = m.part + (int64_t)(3 * f + r) * m.n_part;
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[r][u] = p + u < p1 ? part[p + u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+                    if (p + u < p1) s[r] += v[r][u];
         }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) out[r * m.n_nodes + g] = s[r];
     }
 }
 

@@ -177,8 +177,8 @@ class Mesh:
 
     def profile(self):
         """{kernel: (launches, total_ms)} accumulated since the last reset."""
-        counts = (C.c_int32 * 5)()
-        ms = (C.c_double * 5)()
+        counts = (C.c_int32 * len(_lib.KERNEL_IDS))()
+        ms = (C.c_double * len(_lib.KERNEL_IDS))()
         check(_lib.lib().tlfea_get_profile(self.handle, counts, ms), "tlfea_get_profile")
         return {k: (counts[i], ms[i]) for i, k in enumerate(_lib.KERNEL_IDS)}
 
