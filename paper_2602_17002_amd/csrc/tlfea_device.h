@@ -739,7 +739,10 @@ __device__ __forceinline__ const double *field_src(int f, const CallArgs &c)
 // tile instead of the size of the body keep the per-point gradient sums free
 // of cancellation.  The reference part is read contiguously from the mesh,
 // which stores it per tile node already relative to the tile's first node;
-// the other fields are gathered from the caller's [3][n] arrays.
+// the other fields are gathered from the caller's [3][n] arrays.  The nodes
+// are read in the tile's sorted node order (coalesced) and each record goes
+// to the node's LDS position, which the host chose to spread the per-point
+// gathers of a wavefront over the LDS banks.
 template <int OP, bool DAMPED>
 __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMesh &m, const CallArgs &c,
                                            const TileDesc &t, int tid, int nthr)
@@ -747,13 +750,15 @@ __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMes
     using R = Rec<OP, DAMPED>;
     constexpr int nf = R::nfield;
     const int32_t *gid = m.lnode_gid + t.node_begin;
+    const uint16_t *lpos = m.lnode_pos + t.node_begin;
     const int64_t n = m.n_nodes;
     const int g0 = gid[0];
-    int g[kStagePerThread];
+    int g[kStagePerThread], p[kStagePerThread];
 #pragma unroll
     for (int k = 0; k < kStagePerThread; ++k) {
         const int l = tid + k * nthr;
         g[k] = l < t.n_node ? gid[l] : -1;
+        p[k] = l < t.n_node ? (int)lpos[l] : 0;
     }
     double v[kStagePerThread][3 * R::nfield];
 #pragma unroll
@@ -777,7 +782,7 @@ __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMes
 #pragma unroll
     for (int k = 0; k < kStagePerThread; ++k)
         if (g[k] >= 0) {
-            double *d = sm + (int64_t)(tid + k * nthr) * R::len;
+            double *d = sm + (int64_t)p[k] * R::len;
 #pragma unroll
             for (int j = 0; j < 3 * nf; ++j) d[j] = v[k][j];
         }

@@ -232,6 +232,7 @@ struct HostBuild {
     std::vector<TileDesc> tiles;
     std::vector<uint16_t> conn_local;
     std::vector<int32_t> lnode_gid, lnode_dst, lnode_ptr;
+    std::vector<uint16_t> lnode_pos;
     std::vector<uint16_t> lnode_slot;
     std::vector<int32_t> elem_uid;
     std::vector<int32_t> halo_gid, halo_ptr;
@@ -282,6 +283,71 @@ static int comps_per_round(const ClassRange &c, int op, int64_t lds_dev)
     for (int nc = 3; nc > 1; --nc)
         if ((int64_t)lds_bytes(c, op, nc) <= lds_budget(op, lds_dev)) return nc;
     return 1;
+}
+
+// LDS record positions of a tile's nodes.  A wavefront reads one field of
+// the nodes of its 64 elements with ds_read_b64, which the LDS serves 16
+// lanes per cycle across 16 pairs of 4-byte banks; lanes of one group that
+// hit the same pair at different addresses take extra cycles.  A record at
+// position p starts in pair (p * len) mod 16, and len is odd, so the pair is
+// a bijection of p mod 16 for every operation's record length.  Greedily
+// give each node (most reads first) the class p mod 16 that collides least,
+// weighted by the quadrature points that read it, with the nodes already
+// placed in its 16-lane groups; class sizes are those of 0 .. n_node - 1, so
+// the positions stay dense.  `conn` is the tile's [nen][te] local
+// connectivity (local = index in the sorted node list); returns pos[local].
+static void place_records(const uint16_t *conn, int n_elem, int n_node, int elem, int te, std::vector<uint16_t> &pos)
+{
+    constexpr int kGroup = 16, kPairs = 16;
+    const int nen = nen_of(elem), nq = nq_of(elem);
+    std::vector<int> reads(nen, 0);
+    for (int a = 0; a < nen; ++a)
+        for (int q = 0; q < nq; ++q) {
+            bool nz = false;
+            for (int k = 0; k < 3; ++k) nz |= grad_of(elem, q, a, k) != 0.0;
+            reads[a] += nz ? 1 : 0;
+        }
+    // sets: distinct nodes read by one gather of one 16-lane group
+    std::vector<std::vector<int>> of(n_node);
+    std::vector<int> set_w;
+    std::vector<int> members;
+    for (int a = 0; a < nen; ++a)
+        for (int g0 = 0; g0 < n_elem; g0 += kGroup) {
+            members.clear();
+            for (int i = g0; i < std::min(n_elem, g0 + kGroup); ++i) {
+                const int l = conn[(size_t)a * te + i];
+                if (std::find(members.begin(), members.end(), l) == members.end()) members.push_back(l);
+            }
+            for (int l : members) of[l].push_back((int)set_w.size());
+            set_w.push_back(reads[a]);
+        }
+    std::vector<int> cap(kPairs), cnt(set_w.size() * kPairs, 0), order(n_node), cls(n_node);
+    for (int c = 0; c < kPairs; ++c) cap[c] = n_node / kPairs + (c < n_node % kPairs ? 1 : 0);
+    for (int l = 0; l < n_node; ++l) order[l] = l;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return of[x].size() > of[y].size(); });
+    for (int l : order) {
+        int best = -1;
+        long long best_cost = 0;
+        for (int c = 0; c < kPairs; ++c) {
+            if (!cap[c]) continue;
+            long long z = 0;
+            for (int si : of[l]) z += (long long)set_w[si] * cnt[(size_t)si * kPairs + c];
+            if (best < 0 || z < best_cost) {
+                best = c;
+                best_cost = z;
+            }
+        }
+        cls[l] = best;
+        cap[best]--;
+        for (int si : of[l]) cnt[(size_t)si * kPairs + best]++;
+    }
+    std::vector<int> next(kPairs);
+    for (int c = 0; c < kPairs; ++c) next[c] = c;
+    pos.resize(n_node);
+    for (int l = 0; l < n_node; ++l) {
+        pos[l] = (uint16_t)next[cls[l]];
+        next[cls[l]] += kPairs;
+    }
 }
 
 // Cut the elements `ids` (one block, Morton order) into tiles of at most te
@@ -499,6 +565,17 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                             hb.lnode_slot[base + cnt[l]++] = (uint16_t)(a * te + i);
                         }
                 }
+                // LDS record positions; the elements address records by position
+                {
+                    std::vector<uint16_t> pos;
+                    place_records(&hb.conn_local[t.conn_begin], t.n_elem, t.n_node, keys[k].elem, te, pos);
+                    hb.lnode_pos.insert(hb.lnode_pos.end(), pos.begin(), pos.end());
+                    for (int a = 0; a < nen; ++a)
+                        for (int i = 0; i < t.n_elem; ++i) {
+                            uint16_t &c = hb.conn_local[t.conn_begin + (size_t)a * te + i];
+                            c = pos[c];
+                        }
+                }
                 for (int32_t g : nodes) local[g] = -1;
                 cr.nl_cap = std::max(cr.nl_cap, (int)nodes.size());
                 hb.tiles.push_back(t);
@@ -642,6 +719,7 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
     UP(hb.tiles, d.tiles);
     UP(hb.conn_local, d.conn_local);
     UP(hb.lnode_gid, d.lnode_gid);
+    UP(hb.lnode_pos, d.lnode_pos);
     UP(hb.lnode_dst, d.lnode_dst);
     UP(hb.lnode_ptr, d.lnode_ptr);
     UP(hb.lnode_slot, d.lnode_slot);

@@ -30,8 +30,9 @@ struct BlockDesc {
 // Pointers of the device mesh (all device memory owned by the mesh).
 struct DevMesh {
     const TileDesc *tiles;
-    const uint16_t *conn_local;   // local node index per (tile, a, i)
+    const uint16_t *conn_local;   // LDS record position of the node per (tile, a, i)
     const int32_t *lnode_gid;     // global node of each local node
+    const uint16_t *lnode_pos;    // LDS record position of each local node (a permutation)
     const int32_t *lnode_dst;     // >= 0: global node written directly; < 0: -1 - partial slot
     const int32_t *lnode_ptr;     // CSR offsets into lnode_slot
     const uint16_t *lnode_slot;   // element-force slot = a * te + i
