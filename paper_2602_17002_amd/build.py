@@ -13,6 +13,10 @@ KERNELS = os.path.join(CSRC, "tlfea_kernels.hip")
 HOST = os.path.join(CSRC, "tlfea_host.cpp")
 # (element type, operation) units of tlfea_kernels.hip
 UNITS = [(e, o) for e in (0, 1) for o in (0, 1, 2)]
+# extra compiler flags per operation: the adjoint holds two sets of nodal
+# accumulators, and the scheduler that minimises register pressure keeps it
+# (nearly) free of spills at two waves per SIMD
+OP_FLAGS = {1: ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"]}
 
 
 def hipcc():
@@ -35,7 +39,7 @@ def build(verbose=False, resource_usage=False):
         common += ["-Rpass-analysis=kernel-resource-usage"]
     jobs_list = [(HOST, [], os.path.join(CSRC, "tlfea_host.o"))]
     for e, o in UNITS:
-        jobs_list.append((KERNELS, ["-x", "hip", f"-DTLFEA_ELEM={e}", f"-DTLFEA_OP={o}"],
+        jobs_list.append((KERNELS, ["-x", "hip", f"-DTLFEA_ELEM={e}", f"-DTLFEA_OP={o}"] + OP_FLAGS.get(o, []),
                           os.path.join(CSRC, f"tlfea_kernels_e{e}_o{o}.o")))
     for src, extra, obj in jobs_list:
         cmd = common + extra + ["-c", src, "-o", obj]

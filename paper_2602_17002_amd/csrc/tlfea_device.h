@@ -149,12 +149,13 @@ __device__ __forceinline__ void grad_field(const double *__restrict__ s, const i
     });
 }
 
-// out[a][r] += sum_k Q[r][k] (ds_a/dxi at point Q)_k   (i.e. c P h_a with Q = c P J^{-T})
-template <int ELEM, int QP, int NEN>
+// out[a][r] += sum_k Q[r][k] (ds_a/dxi at point Q)_k   (i.e. c P h_a with Q = c P J^{-T}),
+// for every node but the last when SKIP_LAST (see finish_last_node)
+template <int ELEM, int QP, int NEN, int SKIP_LAST = 0>
 __device__ __forceinline__ void scatter_grad(const m3 &Qm, double (&out)[NEN][3])
 {
     using E = ElemDef<ELEM>;
-    static_for<NEN>([&](auto ac) {
+    static_for<NEN - SKIP_LAST>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         static_for<3>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
@@ -166,6 +167,23 @@ __device__ __forceinline__ void scatter_grad(const m3 &Qm, double (&out)[NEN][3]
             }
         });
     });
+}
+
+// The parent gradients of an element sum to zero at every point (the shape
+// functions sum to one), so the contributions Q g_a of a point to an element
+// vector sum to zero over its nodes, and so does the element vector: the
+// last node's entry is minus the sum of the others.  Accumulating one node
+// fewer saves its registers.
+template <int NEN>
+__device__ __forceinline__ void finish_last_node(double (&out)[NEN][3])
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double sum = 0.0;
+#pragma unroll
+        for (int a = 0; a < NEN - 1; ++a) sum += out[a][r];
+        out[NEN - 1][r] = -sum;
+    }
 }
 
 // Reference geometry at point Q (Sec. 6): J = U dS/dxi, J_p = det J,
@@ -572,6 +590,10 @@ __device__ __forceinline__ void fwd_element(const double *sm, const int (&na)[NE
 //   gtheta_p += c_q Gw : dP/dtheta_p   (P is linear in every parameter row)
 // The viscous terms come first and go straight into Fbar_x and gv, so that
 // the strain rates are dead before the elastic derivative needs registers.
+// With both gx and gv accumulated (damped), the last node of each is formed
+// from the others and K is formed again after the elastic derivative, which
+// keeps the two sets of accumulators within the registers of two waves per
+// SIMD.
 template <int ELEM, int LAW, bool DAMPED, bool WANT_GT, int NEN>
 __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NEN], const Mat &mt,
                                             double (&gx)[NEN][3], double (&gv)[NEN][3], double (&gt)[5])
@@ -617,7 +639,7 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
                     for (int j = 0; j < 3; ++j) A[i][j] = 0.0;
                 acc_mul_ms(F, SvSg, A);              // Fbar_v
                 to_parent(A, K, E::weight(q), T);
-                scatter_grad<ELEM, q>(T, gv);
+                scatter_grad<ELEM, q, NEN, DAMPED ? 1 : 0>(T, gv);
             }
         }
         MRState st;
@@ -635,10 +657,21 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
                 gt[2] += c * (st.J - 1.0) * st.J * ds.GFiT;
             }
         }
+        // K is formed again here rather than kept live across the
+        // elastic derivative (fewer registers at its peak)
         m3 Qm;
-        to_parent(Fb, K, E::weight(q), Qm);
-        scatter_grad<ELEM, q>(Qm, gx);
+        {
+            m3 K2;
+            double d2, r2;
+            ref_geometry<ELEM, q>(sm + R::oX, na, K2, d2, r2);
+            to_parent(Fb, K2, E::weight(q), Qm);
+        }
+        scatter_grad<ELEM, q, NEN, DAMPED ? 1 : 0>(Qm, gx);
     });
+    if constexpr (DAMPED) {
+        finish_last_node(gx);
+        finish_last_node(gv);
+    }
 }
 
 // Tangent: dF = sum_a dx_a h_a^T, dFdot = sum_a dv_a h_a^T,
