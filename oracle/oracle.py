@@ -40,6 +40,8 @@ def lib():
         L.oracle_vjp.argtypes = mesh + [_dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_jvp.argtypes = mesh + [_dp, _dp, _dp, _dp, _dp]
         L.oracle_element_tangent.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_count_inverted.argtypes = [C.c_int, C.c_int64, _dp, C.c_int64, _ip, _dp,
+                                             C.POINTER(C.c_int64), _dp]
         _lib = L
     return _lib
 
@@ -157,6 +159,18 @@ def jvp(X, blocks, x, v, dx=None, dv=None):
         args, keep = _mesh_args(b, X)
         _check(lib().oracle_jvp(*args, _d(x), _d(v), _d(dx), _d(dv), _d(df)), "jvp")
     return df
+
+
+def count_inverted(X, blocks, x):
+    """(number of quadrature points with det F <= 0, smallest |det F| met)."""
+    X = _f64(X); x = _f64(x)
+    n = C.c_int64(0)
+    mn = C.c_double(float("inf"))
+    for b in blocks:
+        conn = np.ascontiguousarray(b.conn, dtype=np.int32)
+        _check(lib().oracle_count_inverted(b.elem, X.shape[1], _d(X), conn.shape[0], conn.ctypes.data_as(_ip),
+                                           _d(x), C.byref(n), C.byref(mn)), "count_inverted")
+    return n.value, mn.value
 
 
 def element_tangent(elem, law, theta, Xe, xe, ve=None, damped=None):

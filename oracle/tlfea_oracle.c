@@ -26,6 +26,7 @@
  *   oracle_stress, oracle_internal_force              pinned
  *   oracle_energy                                     pinned
  *   oracle_element_tangent, oracle_vjp, oracle_jvp    pinned
+ *   oracle_count_inverted                             pinned
  *
  * Layouts: nodal arrays X, x, v, f, w, dx, dv are [3][n_nodes] (row c holds
  * component c of every node); conn is [n_elem][nen] (0-based); theta is
@@ -479,6 +480,35 @@ int oracle_internal_force(int elem, int law, int damped, int64_t n_nodes, const 
             }
         }
     }
+    return OR_OK;
+}
+
+/* Quadrature points whose current deformation gradient has det F <= 0
+ * (an inverted or collapsed element there).  The paper requires J_p > 0 of
+ * the reference map only (Sec. 6) and says nothing of det F; the forward
+ * computes P there anyway, and this count reports such points.  Also
+ * returns the smallest |det F| met, so that a test can see how far every
+ * point is from the sign decision. */
+int oracle_count_inverted(int elem, int64_t n_nodes, const double *X, int64_t n_elem, const int32_t *conn,
+                          const double *x, int64_t *count, double *min_abs_det)
+{
+    elem_t E;
+    if (setup(&E, elem)) return OR_E_INVALID;
+    int64_t n = 0;
+    double mn = INFINITY;
+    for (int64_t e = 0; e < n_elem; ++e) {
+        const int32_t *c = conn + e * E.nen;
+        gather(&E, n_nodes, c, X, x, NULL);
+        for (int q = 0; q < E.nq; ++q) {
+            double H[MAXN][3], F[3][3], Fd[3][3], Jp;
+            if (qp_kinematics(&E, elem, q, H, &Jp, F, Fd)) return OR_E_REF_JACOBIAN;
+            const double d = det3(F);
+            if (d <= 0) ++n;
+            if (fabs(d) < mn) mn = fabs(d);
+        }
+    }
+    *count += n;
+    if (min_abs_det && mn < *min_abs_det) *min_abs_det = mn;
     return OR_OK;
 }
 

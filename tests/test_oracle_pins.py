@@ -349,3 +349,51 @@ def test_assembled_vjp_jvp(elem, law):
             f2 = O.internal_force(X, [b2], x, v)
             ref = np.sum(w * (f2 - f0)) / (0.5 * th_e[p, e])
             assert abs(gt[p, e] - ref) < 1e-8 * max(abs(ref), 1e-300) + 1e-10 * np.abs(w * f0).sum() / th_e[p, e]
+
+
+# ---------------------------------------------------------------- inverted points
+
+def _brute_inverted(elem, X, conn, x):
+    """Points with det F <= 0, from the sign of det(dx/dxi) / det(dX/dxi) where
+    both Jacobians are central differences of the interpolated maps
+    sum_a x_a s_a(xi) (exact for the quadratic T10 and trilinear H8 maps up
+    to rounding); uses only the shape functions and the rule's points."""
+    xi, w = O.quadrature(elem)
+    h = 1e-2
+    n, mn = 0, np.inf
+    for e in range(conn.shape[0]):
+        xe, Xe = x[:, conn[e]], X[:, conn[e]]
+        for q in range(len(w)):
+            D, DX = np.empty((3, 3)), np.empty((3, 3))
+            for k in range(3):
+                p = np.array(xi[q], float); p[k] += h
+                m = np.array(xi[q], float); m[k] -= h
+                ds = (O.shape(elem, p) - O.shape(elem, m)) / (2 * h)
+                D[:, k], DX[:, k] = xe @ ds, Xe @ ds
+            d = np.linalg.det(D) / np.linalg.det(DX)
+            n += int(d <= 0)
+            mn = min(mn, abs(d))
+    return n, mn
+
+
+@pytest.mark.parametrize("elem", [O.T10, O.H8])
+def test_inverted_point_count(elem):
+    if elem == O.T10:
+        X, conn = synth.box_t10(4, 2, 2, size=(0.4, 0.2, 0.2))
+    else:
+        X, conn = synth.box_h8(4, 3, 2, size=(0.4, 0.3, 0.2))
+    b = blk(elem, O.SVK, conn, LAWS["SVK"][1], False)
+    n_qp = conn.shape[0] * len(O.quadrature(elem)[1])
+    # reference state and a rigid motion: none; a reflection or a collapse: all
+    assert O.count_inverted(X, [b], X)[0] == 0
+    R = synth.random_rotation(np.random.default_rng(3))
+    assert O.count_inverted(X, [b], R @ X + 0.3)[0] == 0
+    assert O.count_inverted(X, [b], X * np.array([[1.0], [1.0], [-1.0]]))[0] == n_qp
+    assert O.count_inverted(X, [b], np.zeros_like(X))[0] == n_qp
+    # tangled: a mixed count, equal to the brute-force sign count
+    x = X + np.random.default_rng(1 if elem == O.T10 else 0).normal(0, 0.04, X.shape)
+    n, mn = O.count_inverted(X, [b], x)
+    nb, mnb = _brute_inverted(elem, X, conn, x)
+    assert 0 < n < n_qp
+    assert n == nb
+    assert mn > 1e-3 and abs(mn - mnb) < 1e-9
