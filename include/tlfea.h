@@ -165,6 +165,18 @@ tlfea_status tlfea_tangent_jvp(tlfea_mesh *mesh, const double *x, const double *
  */
 tlfea_status tlfea_node_order(const tlfea_mesh *mesh, int32_t *order);
 
+/*
+ * Number of quadrature points whose current deformation gradient has
+ * det F <= 0 (the element is inverted or collapsed there).  The paper
+ * requires J_p > 0 of the reference map only (Sec. 6); the compute calls
+ * evaluate the laws at such points anyway (J^{-2/3} stays real) and never
+ * trap, and this call reports how many there are.  x: DEVICE [3][n_nodes].
+ * count: DEVICE int64, overwritten (asynchronously, on the stream) with the
+ * total over every block.  F is formed as in the forward; a point whose
+ * det F is within rounding of 0 may be counted either way.
+ */
+tlfea_status tlfea_count_inverted(tlfea_mesh *mesh, const double *x, int64_t *count, void *stream);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *tlfea_last_error(void);
 

@@ -21,7 +21,7 @@ KERNEL_IDS = ("forward_tile", "adjoint_tile", "tangent_tile", "halo", "batched_g
 
 EXPORTS = ("tlfea_create_mesh", "tlfea_destroy_mesh", "tlfea_get_mesh_info", "tlfea_internal_force",
            "tlfea_internal_force_vjp", "tlfea_tangent_jvp", "tlfea_last_error", "tlfea_set_profiling",
-           "tlfea_get_profile", "tlfea_reset_profile", "tlfea_node_order")
+           "tlfea_get_profile", "tlfea_reset_profile", "tlfea_node_order", "tlfea_count_inverted")
 
 
 class Block(C.Structure):
@@ -69,6 +69,8 @@ def lib():
     L.tlfea_internal_force_vjp.restype = C.c_int
     L.tlfea_tangent_jvp.argtypes = [vp, dp, dp, dp, dp, dp, dp, vp]
     L.tlfea_tangent_jvp.restype = C.c_int
+    L.tlfea_count_inverted.argtypes = [vp, dp, vp, vp]
+    L.tlfea_count_inverted.restype = C.c_int
     L.tlfea_last_error.argtypes = []
     L.tlfea_last_error.restype = C.c_char_p
     L.tlfea_set_profiling.argtypes = [vp, C.c_int32]

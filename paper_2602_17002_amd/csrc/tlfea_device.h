@@ -1085,6 +1085,57 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int
     assemble<NEN>(m, t, csr, smem, df, active, c.out0, 0, tid, te, nc);
 }
 
+// Quadrature points with det F <= 0 (inverted or collapsed there).  The
+// paper constrains only the reference map (J_p > 0, Sec. 6); the forward
+// evaluates the laws at such points anyway and this count reports them.  The
+// tile stages X and x, every lane forms F at its element's points as the
+// forward does, and each wavefront adds its count to *count with one
+// integer atomic (the total does not depend on the order).
+template <int ELEM>
+__global__ __launch_bounds__(TLFEA_MAX_TE) void k_inverted(DevMesh m, CallArgs c, int tile0, int ntile, int te,
+                                                          unsigned long long *count)
+{
+    constexpr int NEN = ElemDef<ELEM>::nen;
+    using E = ElemDef<ELEM>;
+    using R = Rec<kOpFwd, false>;
+    extern __shared__ double smem[];
+    const int ti = xcd_tile(blockIdx.x, ntile);
+    if (ti < 0) return;
+    const TileDesc t = m.tiles[tile0 + ti];
+    const int tid = threadIdx.x;
+    stage_tile<kOpFwd, false>(smem, m, c, t, tid, te);
+    __syncthreads();
+    int n = 0;
+    if (tid < t.n_elem) {
+        int na[NEN];
+        load_na<NEN, R::len>(m, t, tid, te, na);
+        point_loop<E::nq>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            m3 K, G, F, cof;
+            double detJ, r;
+            ref_geometry<ELEM, q>(smem + R::oX, na, K, detJ, r);
+            grad_field<ELEM, q>(smem + R::ox, na, G);
+            to_reference(G, K, r, F);
+            cofactor(F, cof);
+            n += det_from_cof(F, cof) <= 0.0 ? 1 : 0;
+        });
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_down(n, off, 64);
+    if ((tid & 63) == 0 && n > 0) atomicAdd(count, (unsigned long long)n);
+}
+
+template <int ELEM>
+hipError_t launch_inverted_class(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m,
+                                 const CallArgs &c, int tile0, unsigned long long *count)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
+    k_inverted<ELEM><<<grid, te, lds, s>>>(m, c, tile0, n_tiles, te, count);
+    return hipGetLastError();
+}
+
 template <int OP, int ELEM, int LAW, bool DAMPED>
 hipError_t launch_one(dim3 grid, int te, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c, int tile0,
                       int ntile, int nl, int nc)

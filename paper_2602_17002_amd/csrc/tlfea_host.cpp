@@ -30,6 +30,11 @@ TLFEA_DECL(1, 1)
 TLFEA_DECL(1, 2)
 #undef TLFEA_DECL
 hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1);
+hipError_t launch_inverted_e0_o0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
+                                 int tile0, unsigned long long *count);
+hipError_t launch_inverted_e1_o0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
+                                 int tile0, unsigned long long *count);
+hipError_t launch_zero_count(hipStream_t s, unsigned long long *count);
 
 static hipError_t launch_tiles(int elem, int law, int damped, int te, int op, int n_tiles, size_t lds, hipStream_t s,
                                const DevMesh &m, const CallArgs &c, int tile0, int nl, int nc)
@@ -896,6 +901,30 @@ extern "C" tlfea_status tlfea_tangent_jvp(tlfea_mesh *m, const double *x, const 
     CallArgs c{};
     c.x = x; c.v = v; c.theta = theta; c.dx = dx; c.dv = m->any_damped ? dv : nullptr; c.out0 = df;
     return run(m, kOpJvp, c, stream);
+}
+
+extern "C" tlfea_status tlfea_count_inverted(tlfea_mesh *m, const double *x, int64_t *count, void *stream)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (!count) return fail(TLFEA_E_INVALID, "count is NULL");
+    if (m->n_nodes > 0 && !x) return fail(TLFEA_E_INVALID, "x is required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != m->device) return fail(TLFEA_E_INVALID, "current device %d differs from the mesh's device %d", dev, m->device);
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(count);
+    hipError_t e = launch_zero_count(s, cnt);
+    if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    CallArgs c{};
+    c.x = x;
+    for (const ClassRange &cr : m->classes) {
+        const size_t lds = (size_t)cr.nl_cap * record_len(kOpFwd, false) * sizeof(double);
+        e = cr.elem == kT10 ? launch_inverted_e0_o0(cr.te, cr.tile_count, lds, s, m->dm, c, cr.tile_begin, cnt)
+                            : launch_inverted_e1_o0(cr.te, cr.tile_count, lds, s, m->dm, c, cr.tile_begin, cnt);
+        if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    }
+    return TLFEA_OK;
 }
 
 // ------------------------------------------------------------------ autotune

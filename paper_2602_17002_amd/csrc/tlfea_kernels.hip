@@ -22,7 +22,24 @@ hipError_t TLFEA_CAT(launch_tiles, TLFEA_ELEM, TLFEA_OP)(int law, int damped, in
     return launch_class<TLFEA_OP, TLFEA_ELEM>(law, damped, te, n_tiles, lds, s, m, c, tile0, nl, nc);
 }
 
+#if TLFEA_OP == 0
+hipError_t TLFEA_CAT(launch_inverted, TLFEA_ELEM, TLFEA_OP)(int te, int n_tiles, size_t lds, hipStream_t s,
+                                                             const DevMesh &m, const CallArgs &c, int tile0,
+                                                             unsigned long long *count)
+{
+    return launch_inverted_class<TLFEA_ELEM>(te, n_tiles, lds, s, m, c, tile0, count);
+}
+#endif
+
 #if TLFEA_ELEM == 0 && TLFEA_OP == 0
+__global__ void k_zero_count(unsigned long long *count) { *count = 0ull; }
+
+hipError_t launch_zero_count(hipStream_t s, unsigned long long *count)
+{
+    k_zero_count<<<1, 1, 0, s>>>(count);
+    return hipGetLastError();
+}
+
 // Nodes shared between tiles (and nodes no element touches): sum the node's
 // partial slots, which are contiguous and in tile order.  One lane per node;
 // up to two output fields.  Partials are read eight at a time (every load of

@@ -159,6 +159,15 @@ class Mesh:
               "tlfea_internal_force_vjp")
         return gx, gv, gt
 
+    def count_inverted(self, x, out=None, stream=None):
+        """Device int64 tensor [1]: quadrature points with det F <= 0."""
+        x = self._nodal(x, "x")
+        if out is None:
+            out = torch.empty(1, dtype=torch.int64, device=self.device)
+        check(_lib.lib().tlfea_count_inverted(self.handle, _ptr(x), _ptr(out), self._stream(stream)),
+              "tlfea_count_inverted")
+        return out
+
     def jvp(self, x, v=None, dx=None, dv=None, theta=None, out=None, stream=None):
         """df = (df/dx) dx + (df/dv) dv."""
         x = self._nodal(x, "x")

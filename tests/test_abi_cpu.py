@@ -117,6 +117,7 @@ def test_compute_calls_reject_null_mesh():
     assert L.tlfea_internal_force(None, None, None, None, None, None) == -1
     assert L.tlfea_internal_force_vjp(None, None, None, None, None, None, None, None, None) == -1
     assert L.tlfea_tangent_jvp(None, None, None, None, None, None, None, None) == -1
+    assert L.tlfea_count_inverted(None, None, None, None) == -1
     assert L.tlfea_get_mesh_info(None, None) == -1
     assert L.tlfea_set_profiling(None, 1) == -1
     L.tlfea_destroy_mesh(None)   # no-op

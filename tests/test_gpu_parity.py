@@ -183,6 +183,37 @@ def test_degenerate_meshes():
     assert np.all(to_host(m.internal_force(to_dev(x), to_dev(v))) == 0)
 
 
+@pytest.mark.parametrize("tile", [64, 256])
+def test_count_inverted_matches_oracle(tile):
+    """Integer count of points with det F <= 0, exact against the oracle on
+    tangled T10 and H8 boxes (seeds whose smallest |det F| is far from the
+    rounding of either side), plus the reference, reflected, collapsed and
+    multi-block cases."""
+    say("count_inverted tile", tile)
+    cases = []
+    for elem, n, size, seed in ((synth.T10, (4, 2, 2), (0.4, 0.2, 0.2), 1), (synth.H8, (4, 3, 2), (0.4, 0.3, 0.2), 0)):
+        X, conn = (synth.box_t10 if elem == synth.T10 else synth.box_h8)(*n, size=size)
+        b = synth.Block(elem, synth.SVK, conn, LAWS["SVK"][1], damped=False)
+        b.tile_elems = tile
+        x = X + np.random.default_rng(seed).normal(0, 0.04, X.shape)
+        cases.append((X, [b], x))
+    # the two bodies side by side in one mesh
+    X0, b0, x0 = cases[0]
+    X1, b1, x1 = cases[1]
+    bb = copy.copy(b1[0]); bb.conn = b1[0].conn + X0.shape[1]
+    cases.append((np.concatenate([X0, X1], 1), [b0[0], bb], np.concatenate([x0, x1], 1)))
+    from paper_2602_17002_amd import Mesh
+    for X, blocks, x in cases:
+        n_qp = sum(bl.conn.shape[0] * len(O.quadrature(bl.elem)[1]) for bl in blocks)
+        m = Mesh(X, blocks)
+        ref, mn = O.count_inverted(X, blocks, x)
+        assert 0 < ref < n_qp and mn > 1e-3
+        assert int(m.count_inverted(to_dev(x)).item()) == ref
+        assert int(m.count_inverted(to_dev(X)).item()) == 0
+        assert int(m.count_inverted(to_dev(X * np.array([[1.0], [-1.0], [1.0]]))).item()) == n_qp
+        assert int(m.count_inverted(to_dev(np.zeros_like(X))).item()) == n_qp
+
+
 def test_multibody_batched_graph_equals_plain_and_oracle():
     from paper_2602_17002_amd import BATCHED, Mesh
     import torch
