@@ -251,13 +251,15 @@ static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
 // few enough that every operation's node records and assembly tables stay
 // within its LDS budget.
 // LDS budget of one workgroup of an operation: the device's per-workgroup
-// limit, and at most the share of a 160 KiB compute-unit LDS that lets the
-// workgroups the kernel's register use allows (three for the forward, two
-// for the adjoint and the tangent) be resident together.
-static int64_t lds_budget(int op, int64_t lds_dev)
+// limit, and at most the share of a 160 KiB compute-unit LDS that lets as
+// many workgroups be resident as the kernel's register use allows (three
+// waves per SIMD for the forward, two for the adjoint and the tangent; a
+// workgroup of te elements has te / 64 waves).
+static int64_t lds_budget(int op, int te, int64_t lds_dev)
 {
-    static const int wgs[3] = {3, 2, 2};
-    return std::min<int64_t>(lds_dev, 163840 / wgs[op]);
+    const int64_t waves_per_cu = op == kOpFwd ? 12 : 8;
+    const int64_t wgs = std::max<int64_t>(1, waves_per_cu * 64 / te);
+    return std::min<int64_t>(lds_dev, 163840 / wgs);
 }
 
 static int nl_limit(int elem, int te, int damped, int64_t lds_dev)
@@ -267,7 +269,7 @@ static int nl_limit(int elem, int te, int damped, int64_t lds_dev)
     for (int op = kOpFwd; op <= kOpJvp; ++op) {
         const int64_t fixed = 4 + (int64_t)nen * te * 2;
         const int64_t per_node = 8 * (int64_t)record_len(op, damped != 0) + 8;
-        nl = std::min(nl, (lds_budget(op, lds_dev) - fixed) / per_node);
+        nl = std::min(nl, (lds_budget(op, te, lds_dev) - fixed) / per_node);
     }
     return (int)nl;
 }
@@ -286,7 +288,7 @@ static size_t lds_bytes(const ClassRange &c, int op, int nc)
 static int comps_per_round(const ClassRange &c, int op, int64_t lds_dev)
 {
     for (int nc = 3; nc > 1; --nc)
-        if ((int64_t)lds_bytes(c, op, nc) <= lds_budget(op, lds_dev)) return nc;
+        if ((int64_t)lds_bytes(c, op, nc) <= lds_budget(op, c.te, lds_dev)) return nc;
     return 1;
 }
 
