@@ -931,7 +931,7 @@ extern "C" tlfea_status tlfea_count_inverted(tlfea_mesh *m, const double *x, int
 
 // ------------------------------------------------------------------ autotune
 
-// Time forward + adjoint per class for one candidate tile size.
+// Time forward + adjoint + tangent per class for one candidate tile size.
 static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vector<double> &t_cls)
 {
     const size_t nb = sizeof(double) * 3 * (size_t)m->n_nodes;
@@ -950,9 +950,9 @@ static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vecto
     t_cls.assign(m->classes.size(), 0.0);
     for (size_t k = 0; k < m->classes.size(); ++k) {
         const ClassRange &cr = m->classes[k];
-        for (int op = kOpFwd; op <= kOpVjp; ++op) {
+        for (int op = kOpFwd; op <= kOpJvp; ++op) {
             CallArgs c{};
-            c.x = x; c.v = v; c.w = w; c.out0 = o0; c.out1 = o1;
+            c.x = x; c.v = v; c.w = w; c.dx = w; c.dv = v; c.out0 = o0; c.out1 = op == kOpVjp ? o1 : nullptr;
             const size_t lds = lds_bytes(cr, op, cr.nc[op]);
             float best = 1e30f;
             for (int rep = 0; rep < 4; ++rep) {
@@ -986,8 +986,8 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
     for (int b = 0; b < n_blocks; ++b) te[b] = blocks[b].tile_elems ? blocks[b].tile_elems : default_te(blocks[b].elem);
     if (!(flags & TLFEA_AUTOTUNE)) return create_with(n_nodes, X, n_blocks, blocks, flags, te, out);
     // Autotune: per (element, law, damping) class, the tile size with the
-    // smallest forward + adjoint time over the class's own tiles; blocks that
-    // fix tile_elems keep it.
+    // smallest forward + adjoint + tangent time over the class's own tiles;
+    // blocks that fix tile_elems keep it.
     const int cand[4] = {64, 128, 192, 256};
     std::vector<double> best_t(n_blocks, 1e300);
     std::vector<int> best_te = te;
