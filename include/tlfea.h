@@ -160,8 +160,9 @@ tlfea_status tlfea_tangent_jvp(tlfea_mesh *mesh, const double *x, const double *
  * (HOST int32[n_nodes], written).  The mesh is unchanged.  Renumbering X,
  * the connectivity and every nodal array once with it, and creating the
  * mesh again from the renumbered data, makes the kernels' node gathers and
- * stores coalesced; results are the same up to the renumbering (the tiles
- * and their summation order do not depend on node numbers).
+ * stores coalesced.  The tiles and their summation order do not depend on
+ * node numbers; the node each tile's coordinates are taken relative to may,
+ * so results agree with those of the original numbering to rounding.
  */
 tlfea_status tlfea_node_order(const tlfea_mesh *mesh, int32_t *order);
 

@@ -183,6 +183,27 @@ def test_degenerate_meshes():
     assert np.all(to_host(m.internal_force(to_dev(x), to_dev(v))) == 0)
 
 
+def test_node_order_renumbering():
+    """tlfea_node_order is a permutation; a mesh built from the renumbered
+    problem gives the renumbered outputs (to rounding) and matches the oracle."""
+    p = make_problem(synth.T10, "NH", True, n=(9, 7, 4), seed=11)
+    say("node order", p.name, p.n_elem)
+    m = mesh_of(p)
+    order = m.node_order()
+    assert np.array_equal(np.sort(order), np.arange(p.n_nodes))
+    q = p.renumbered(order)
+    mq = mesh_of(q)
+    f = to_host(m.internal_force(to_dev(p.x), to_dev(p.v)))
+    fq = to_host(mq.internal_force(to_dev(q.x), to_dev(q.v)))
+    gx, gv, _ = m.vjp(to_dev(p.x), to_dev(p.v), to_dev(p.w), want_theta=False)
+    gxq, gvq, _ = mq.vjp(to_dev(q.x), to_dev(q.v), to_dev(q.w), want_theta=False)
+    assert rel(fq, f[:, order]) <= 1e-13
+    assert rel(to_host(gxq), to_host(gx)[:, order]) <= 1e-13
+    assert rel(to_host(gvq), to_host(gv)[:, order]) <= 1e-13
+    Xc, xc = centred(q.X, q.x)
+    assert rel(fq, O.internal_force(Xc, q.blocks, xc, q.v)) <= TOL
+
+
 @pytest.mark.parametrize("tile", [64, 256])
 def test_count_inverted_matches_oracle(tile):
     """Integer count of points with det F <= 0, exact against the oracle on
@@ -296,7 +317,8 @@ def _full_size(cfg):
 @pytest.mark.parametrize("cfg", ["C2", "C4"])
 def test_full_size_sampled_against_oracle(cfg):
     """The benchmark's mesh sizes and launch configuration (library default
-    tiling): forward, adjoint (gx, gv, gtheta) and tangent on the whole mesh,
+    tiling, nodes renumbered once with tlfea_node_order as the benchmark
+    does): forward, adjoint (gx, gv, gtheta) and tangent on the whole mesh,
     checked at sampled nodes (random ones plus boundary ones) and at the
     elements incident to them, each evaluated by the oracle on its own patch."""
     import torch
@@ -305,6 +327,15 @@ def test_full_size_sampled_against_oracle(cfg):
     blk = p.blocks[0]
     damped = blk.damped
     say(cfg, "elements", p.n_elem, "nodes", p.n_nodes)
+    m0 = mesh_of(p)
+    order = m0.node_order()
+    m0.close()
+    # the same physical nodes are sampled under either numbering
+    nodes = sample_nodes(p, 48, 16, seed=13)
+    inv = np.empty_like(order)
+    inv[order] = np.arange(order.size)
+    nodes = inv[nodes]
+    p = p.renumbered(order)
     m = mesh_of(p)
     x, v, w = to_dev(p.x), to_dev(p.v), to_dev(p.w)
     th = to_dev(p.theta_all())
@@ -316,7 +347,6 @@ def test_full_size_sampled_against_oracle(cfg):
     torch.cuda.synchronize()
     dxh = to_host(dx)
     p.dx = dxh
-    nodes = sample_nodes(p, 48, 16, seed=13)
     got = {k: [] for k in ("f", "gx", "gv", "df", "gt")}
     ref = {k: [] for k in got}
     for n in nodes:
