@@ -772,7 +772,9 @@ __device__ __forceinline__ const double *field_src(int f, const CallArgs &c)
 // tile instead of the size of the body keep the per-point gradient sums free
 // of cancellation.  The reference part is read contiguously from the mesh,
 // which stores it per tile node already relative to the tile's first node;
-// the other fields are gathered from the caller's [3][n] arrays.  The nodes
+// the other fields are gathered from the caller's [3][n] arrays.  The mesh's
+// per-tile arrays are read once per call and are loaded non-temporally, which
+// leaves the L2 to the node data that neighbouring tiles share.  The nodes
 // are read in the tile's sorted node order (coalesced) and each record goes
 // to the node's LDS position, which the host chose to spread the per-point
 // gathers of a wavefront over the LDS banks.
@@ -790,15 +792,16 @@ __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMes
 #pragma unroll
     for (int k = 0; k < kStagePerThread; ++k) {
         const int l = tid + k * nthr;
-        g[k] = l < t.n_node ? gid[l] : -1;
-        p[k] = l < t.n_node ? (int)lpos[l] : 0;
+        g[k] = l < t.n_node ? __builtin_nontemporal_load(gid + l) : -1;
+        p[k] = l < t.n_node ? (int)__builtin_nontemporal_load(lpos + l) : 0;
     }
     double v[kStagePerThread][3 * R::nfield];
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
         const double *xt = m.Xt + cc * m.n_tnode + t.node_begin;
 #pragma unroll
-        for (int k = 0; k < kStagePerThread; ++k) v[k][R::oX + cc] = g[k] >= 0 ? xt[tid + k * nthr] : 0.0;
+        for (int k = 0; k < kStagePerThread; ++k)
+            v[k][R::oX + cc] = g[k] >= 0 ? __builtin_nontemporal_load(xt + tid + k * nthr) : 0.0;
     }
 #pragma unroll
     for (int f = 1; f < nf; ++f) {
@@ -826,7 +829,7 @@ template <int NEN, int LEN>
 __device__ __forceinline__ void load_na(const DevMesh &m, const TileDesc &t, int i, int te, int (&na)[NEN])
 {
 #pragma unroll
-    for (int a = 0; a < NEN; ++a) na[a] = (int)m.conn_local[t.conn_begin + a * te + i] * LEN;
+    for (int a = 0; a < NEN; ++a) na[a] = (int)__builtin_nontemporal_load(m.conn_local + t.conn_begin + a * te + i) * LEN;
 }
 
 // The tile's assembly tables, copied to LDS while the node records are
@@ -851,9 +854,10 @@ __device__ __forceinline__ TileCsr csr_layout(double *smem, int nl, int rec_len,
 }
 
 // Every load of a thread is issued before its LDS stores (a loop of
-// load-then-store would wait for one global round trip per iteration).  The
-// slot ids are copied as 32-bit words; a tile's entries start at an even
-// global index (the host pads every tile's list to an even length).
+// load-then-store would wait for one global round trip per iteration); the
+// tables are read once per call and loaded non-temporally.  The slot ids
+// are copied as 32-bit words; a tile's entries start at an even global
+// index (the host pads every tile's list to an even length).
 template <int NEN>
 __device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, const TileDesc &t, int tid, int nthr)
 {
@@ -863,12 +867,12 @@ __device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, co
 #pragma unroll
     for (int k = 0; k <= kStagePerThread; ++k) {
         const int l = tid + k * nthr;
-        pv[k] = l <= t.n_node ? gptr[l] - base : 0;
+        pv[k] = l <= t.n_node ? __builtin_nontemporal_load(gptr + l) - base : 0;
     }
 #pragma unroll
     for (int k = 0; k < kStagePerThread; ++k) {
         const int l = tid + k * nthr;
-        dv[k] = l < t.n_node ? m.lnode_dst[t.node_begin + l] : 0;
+        dv[k] = l < t.n_node ? __builtin_nontemporal_load(m.lnode_dst + t.node_begin + l) : 0;
     }
     // NEN * n_elem entries = NEN * n_elem / 2 words; at most NEN / 2 words per thread
     constexpr int W = (NEN + 1) / 2;
@@ -878,7 +882,7 @@ __device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, co
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         const int e = tid + k * nthr;
-        wv[k] = e < n_words ? gw[e] : 0u;
+        wv[k] = e < n_words ? __builtin_nontemporal_load(gw + e) : 0u;
     }
 #pragma unroll
     for (int k = 0; k <= kStagePerThread; ++k)
