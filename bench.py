@@ -16,7 +16,7 @@ The line also carries the multibody comparison (skip with --no-batched): 512 bod
 force of every body, timed as one batched mesh (one hipGraph replay) and as
 one plain mesh per body launched back to back on one stream.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 
 --pmc-summary DIR writes the rocprofv3 summaries under profiles/ from the
 output folders of a kernel-trace run and two counter runs.
@@ -392,7 +392,7 @@ def main():
         pmc_summary(*args.pmc_summary, json.loads(args.commands))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 

@@ -59,7 +59,7 @@ typedef enum {
     TLFEA_E_REF_JACOBIAN = -3,   /* J_p <= 0 at a quadrature point (Sec. 6)   */
     TLFEA_E_NOMEM = -4,          /* host or device allocation failed          */
     TLFEA_E_DEVICE = -5,         /* HIP runtime error (also a prior fault)    */
-    TLFEA_E_UNSUPPORTED = -6     /* valid request this build does not handle  */
+    TLFEA_E_UNSUPPORTED = -6     /* valid request the library does not handle */
 } tlfea_status;
 
 enum { TLFEA_T10 = 0, TLFEA_H8 = 1 };          /* element types            */
