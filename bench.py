@@ -122,13 +122,15 @@ def log(*a):
 
 
 def source_hash():
-    """sha256 of the HIP library sources (ties counter summaries to a build)."""
+    """sha256 of the HIP library sources and of the build script that holds
+    their compiler flags (ties counter summaries to a build)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(CSRC, "*"))):
-        if p.endswith((".h", ".hip", ".cpp")):
-            h.update(os.path.basename(p).encode())
-            with open(p, "rb") as fh:
-                h.update(fh.read())
+    files = sorted(p for p in glob.glob(os.path.join(CSRC, "*")) if p.endswith((".h", ".hip", ".cpp")))
+    files.append(os.path.join(os.path.dirname(CSRC), "build.py"))
+    for p in files:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
