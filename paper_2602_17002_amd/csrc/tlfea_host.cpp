@@ -760,40 +760,52 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
 
 // ------------------------------------------------------------------ launching
 
+// Owns a pair of timing events until they are handed to the mesh's pending
+// list; destroys them on any early return.
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~EventPair()
+    {
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+    }
+};
+
+// One kernel launch, bracketed by events on the stream when timed (kernel
+// id kid of the profile).
+template <typename Launch>
+static tlfea_status timed_launch(tlfea_mesh *m, int kid, hipStream_t s, bool timed, const char *what, Launch &&launch)
+{
+    EventPair ev;
+    if (timed) {
+        HIP_TRY(hipEventCreate(&ev.e0));
+        HIP_TRY(hipEventCreate(&ev.e1));
+        HIP_TRY(hipEventRecord(ev.e0, s));
+    }
+    const hipError_t e = launch();
+    if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "%s launch: %s", what, hipGetErrorString(e));
+    if (timed) {
+        HIP_TRY(hipEventRecord(ev.e1, s));
+        m->pending[kid].push_back({ev.e0, ev.e1});
+        ev.e0 = ev.e1 = nullptr;
+    }
+    return TLFEA_OK;
+}
+
 static tlfea_status enqueue(tlfea_mesh *m, int op, const CallArgs &c, hipStream_t s, bool timed)
 {
-    const int kid = op;   // kernel id: 0 fwd, 1 vjp, 2 jvp
+    // kernel ids: 0 forward, 1 adjoint, 2 tangent (= op), 3 shared nodes
     for (const ClassRange &cr : m->classes) {
         const size_t lds = lds_bytes(cr, op, cr.nc[op]);
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed) {
-            HIP_TRY(hipEventCreate(&e0));
-            HIP_TRY(hipEventCreate(&e1));
-            HIP_TRY(hipEventRecord(e0, s));
-        }
-        hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, s, m->dm, c,
-                                    cr.tile_begin, cr.nl_cap, cr.nc[op]);
-        if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "tile kernel launch: %s", hipGetErrorString(e));
-        if (timed) {
-            HIP_TRY(hipEventRecord(e1, s));
-            m->pending[kid].push_back({e0, e1});
-        }
+        tlfea_status st = timed_launch(m, op, s, timed, "tile kernel", [&] {
+            return launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, s, m->dm, c,
+                                cr.tile_begin, cr.nl_cap, cr.nc[op]);
+        });
+        if (st != TLFEA_OK) return st;
     }
     double *o1 = (op == kOpVjp) ? c.out1 : nullptr;
-    if (m->dm.n_halo > 0 && (c.out0 || o1)) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed) {
-            HIP_TRY(hipEventCreate(&e0));
-            HIP_TRY(hipEventCreate(&e1));
-            HIP_TRY(hipEventRecord(e0, s));
-        }
-        hipError_t e = launch_halo(s, m->dm, c.out0, o1);
-        if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "halo kernel launch: %s", hipGetErrorString(e));
-        if (timed) {
-            HIP_TRY(hipEventRecord(e1, s));
-            m->pending[3].push_back({e0, e1});
-        }
-    }
+    if (m->dm.n_halo > 0 && (c.out0 || o1))
+        return timed_launch(m, 3, s, timed, "shared-node kernel", [&] { return launch_halo(s, m->dm, c.out0, o1); });
     return TLFEA_OK;
 }
 
@@ -846,18 +858,8 @@ static tlfea_status run(tlfea_mesh *m, int op, const CallArgs &c, void *stream)
         hit = &m->graphs.back();
     }
     hit->stamp = ++m->stamp;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (m->prof) {
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
-        HIP_TRY(hipEventRecord(e0, s));
-    }
-    HIP_TRY(hipGraphLaunch(hit->exec, s));
-    if (m->prof) {
-        HIP_TRY(hipEventRecord(e1, s));
-        m->pending[4].push_back({e0, e1});
-    }
-    return TLFEA_OK;
+    hipGraphExec_t exec = hit->exec;
+    return timed_launch(m, 4, s, m->prof, "graph", [&] { return hipGraphLaunch(exec, s); });
 }
 
 static tlfea_status check_mesh(const tlfea_mesh *m)
@@ -935,18 +937,23 @@ extern "C" tlfea_status tlfea_count_inverted(tlfea_mesh *m, const double *x, int
 static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vector<double> &t_cls)
 {
     const size_t nb = sizeof(double) * 3 * (size_t)m->n_nodes;
-    double *x = nullptr, *v = nullptr, *w = nullptr, *o0 = nullptr, *o1 = nullptr;
-    HIP_TRY(hipMalloc(&x, nb));
-    HIP_TRY(hipMalloc(&v, nb));
-    HIP_TRY(hipMalloc(&w, nb));
-    HIP_TRY(hipMalloc(&o0, nb));
-    HIP_TRY(hipMalloc(&o1, nb));
+    struct Buffers {   // freed on every return
+        double *p[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        ~Buffers()
+        {
+            for (double *q : p)
+                if (q) hipFree(q);
+        }
+    } buf;
+    for (double *&q : buf.p) HIP_TRY(hipMalloc(&q, nb));
+    double *x = buf.p[0], *v = buf.p[1], *w = buf.p[2], *o0 = buf.p[3], *o1 = buf.p[4];
     HIP_TRY(hipMemcpy(x, X_host, nb, hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(v, 0, nb));
     HIP_TRY(hipMemset(w, 0, nb));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.e0));
+    HIP_TRY(hipEventCreate(&ev.e1));
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     t_cls.assign(m->classes.size(), 0.0);
     for (size_t k = 0; k < m->classes.size(); ++k) {
         const ClassRange &cr = m->classes[k];
@@ -969,9 +976,6 @@ static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vecto
             t_cls[k] += best;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(x); hipFree(v); hipFree(w); hipFree(o0); hipFree(o1);
     return TLFEA_OK;
 }
 
