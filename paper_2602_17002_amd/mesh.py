@@ -121,6 +121,19 @@ class Mesh:
             raise ValueError(f"{name} must have shape (5, {self.n_elem}), got {tuple(t.shape)}")
         return t.contiguous()
 
+    def _out(self, t, name, shape, dtype=torch.float64):
+        """An output buffer the library writes in place: right dtype, device,
+        shape and contiguous (a copy would silently lose the result)."""
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != self.device:
+            raise TypeError(f"{name} must be a {dtype} tensor on {self.device}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
     def _stream(self, stream):
         s = torch.cuda.current_stream(self.device) if stream is None else stream
         return C.c_void_p(s.cuda_stream)
@@ -134,7 +147,7 @@ class Mesh:
         x = self._nodal(x, "x")
         v = self._nodal(v, "v", required=False)
         theta = self._theta(theta)
-        f = self._empty_nodal() if out is None else self._nodal(out, "out")
+        f = self._empty_nodal() if out is None else self._out(out, "out", (3, self.n_nodes))
         check(_lib.lib().tlfea_internal_force(self.handle, _ptr(x), _ptr(v), _ptr(theta), _ptr(f),
                                               self._stream(stream)), "tlfea_internal_force")
         return f
@@ -148,6 +161,9 @@ class Mesh:
         gx = gv = gt = None
         if out is not None:
             gx, gv, gt = out
+            gx = self._out(gx, "gx", (3, self.n_nodes))
+            gv = self._out(gv, "gv", (3, self.n_nodes))
+            gt = self._out(gt, "gtheta", (5, self.n_elem))
         if want_x and gx is None:
             gx = self._empty_nodal()
         if want_v and gv is None:
@@ -164,6 +180,7 @@ class Mesh:
         x = self._nodal(x, "x")
         if out is None:
             out = torch.empty(1, dtype=torch.int64, device=self.device)
+        out = self._out(out, "out", (1,), torch.int64)
         check(_lib.lib().tlfea_count_inverted(self.handle, _ptr(x), _ptr(out), self._stream(stream)),
               "tlfea_count_inverted")
         return out
@@ -175,7 +192,7 @@ class Mesh:
         dx = self._nodal(dx, "dx", required=False)
         dv = self._nodal(dv, "dv", required=False)
         theta = self._theta(theta)
-        df = self._empty_nodal() if out is None else self._nodal(out, "out")
+        df = self._empty_nodal() if out is None else self._out(out, "out", (3, self.n_nodes))
         check(_lib.lib().tlfea_tangent_jvp(self.handle, _ptr(x), _ptr(v), _ptr(theta), _ptr(dx), _ptr(dv),
                                            _ptr(df), self._stream(stream)), "tlfea_tangent_jvp")
         return df
