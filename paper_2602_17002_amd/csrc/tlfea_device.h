@@ -1017,8 +1017,11 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LA
     assemble<NEN>(m, t, csr, smem, fe, active, c.out0, 0, tid, te, nc);
 }
 
+// Two waves per SIMD (256 registers); the damped Mooney-Rivlin adjoint, which
+// needs more than that and spilled 488 B per lane there, runs at one wave
+// per SIMD with its whole state in registers (24 % faster).
 template <int ELEM, int LAW, bool DAMPED, bool WANT_GT>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LAW == 1 && DAMPED ? 1 : 2))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpVjp, DAMPED>;
@@ -1060,9 +1063,12 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2)
 }
 
 // The tangent stages dx (zeros when null) and, for damped blocks, dv (zeros
-// when null), so one instantiation serves every combination.
+// when null), so one instantiation serves every combination.  At least two
+// waves per SIMD: left free, the compiler gave the Mooney-Rivlin tangent one
+// wave and 512 registers, which ran about 20 % slower than two waves with a
+// small spill.
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2))) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpJvp, DAMPED>;
