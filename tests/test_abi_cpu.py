@@ -131,3 +131,21 @@ def test_python_wrapper_raises_typed_error(box):
     with pytest.raises(TlfeaError) as ei:
         Mesh(X, [blk])
     assert ei.value.status == -2
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/tlfea.h compiles as C99 on its own (no C++ or torch types)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include <stddef.h>\n#include "tlfea.h"\n'
+                   "int use(tlfea_mesh *m, const double *x, double *f, void *s)\n"
+                   "{ tlfea_block b = {TLFEA_T10, TLFEA_NH, 0, NULL, {1, 0, 1, 0, 0}, 0, 0};\n"
+                   "  (void)b; return (int)tlfea_internal_force(m, x, NULL, NULL, f, s); }\n")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", inc, "-c", str(src),
+                        "-o", str(tmp_path / "use.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
