@@ -999,10 +999,14 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LA
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
+    // staging issues long-latency loads: its waves go first while other
+    // tiles on the compute unit compute
+    __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
     stage_csr<NEN>(csr, m, t, tid, te);
     stage_tile<kOpFwd, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
     double fe[NEN][3];
 #pragma unroll
     for (int a = 0; a < NEN; ++a) fe[a][0] = fe[a][1] = fe[a][2] = 0.0;
@@ -1030,10 +1034,14 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LA
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
+    // staging issues long-latency loads: its waves go first while other
+    // tiles on the compute unit compute
+    __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
     stage_csr<NEN>(csr, m, t, tid, te);
     stage_tile<kOpVjp, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
     double gx[NEN][3], gv[NEN][3], gt[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < NEN; ++a)
@@ -1077,10 +1085,14 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2)
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
+    // staging issues long-latency loads: its waves go first while other
+    // tiles on the compute unit compute
+    __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
     stage_csr<NEN>(csr, m, t, tid, te);
     stage_tile<kOpJvp, DAMPED>(smem, m, c, t, tid, te);
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
     double df[NEN][3];
 #pragma unroll
     for (int a = 0; a < NEN; ++a) df[a][0] = df[a][1] = df[a][2] = 0.0;
