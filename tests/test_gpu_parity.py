@@ -310,11 +310,28 @@ def test_autograd_function():
     assert rel(tangent, ref) <= TOL
 
 
+def _h8_body():
+    """A large H8 body (64x64x32 cells = 131,072 trilinear hexahedra, 2x2x2
+    Gauss), Mooney-Rivlin with Kelvin-Voigt damping, under a rigid motion and
+    a 3 % smooth deformation: the batched sets' other element type and the
+    paper's general law, at a size that fills the GPU."""
+    rng = np.random.default_rng(np.random.SeedSequence(1006))
+    n = (64, 64, 32)
+    X, conn = synth.box_h8(*n, size=tuple(0.01 * k for k in n))
+    x = synth.sinusoidal_state(X, 0.03, rng)
+    v = rng.normal(0.0, 0.01, X.shape)
+    b = synth.Block(synth.H8, synth.MR, conn, np.array([1.2e6, 0.45e6, 1.72667e7, 1.0e4, 3.0e3]), damped=True)
+    p = synth.Problem("H8-MR-KV-131k", X, x, v, [b], cell=0.01)
+    p.w = rng.standard_normal(X.shape)
+    p.dx = rng.standard_normal(X.shape) * 0.01
+    return p
+
+
 def _full_size(cfg):
-    return {"C2": synth.config_c2, "C4": synth.config_c4}[cfg]()
+    return {"C2": synth.config_c2, "C4": synth.config_c4, "H8": _h8_body}[cfg]()
 
 
-@pytest.mark.parametrize("cfg", ["C2", "C4"])
+@pytest.mark.parametrize("cfg", ["C2", "C4", "H8"])
 def test_full_size_sampled_against_oracle(cfg):
     """The benchmark's mesh sizes and launch configuration (library default
     tiling, nodes renumbered once with tlfea_node_order as the benchmark
