@@ -266,6 +266,12 @@ static int nl_limit(int elem, int te, int damped, int64_t lds_dev)
 {
     const int nen = nen_of(elem);
     int64_t nl = (int64_t)kStagePerThread * te;
+    // full 256-element tiles: at most 600 nodes even where the LDS would hold
+    // more.  Compact T10 tiles have about 550 (p99 670 without the cap), and
+    // letting the ragged ones grow further made the undamped forward 8 %
+    // slower.  Smaller tiles have proportionally more surface nodes and keep
+    // only the LDS limit.
+    if (te == 256) nl = std::min<int64_t>(nl, 600);
     for (int op = kOpFwd; op <= kOpJvp; ++op) {
         const int64_t fixed = 4 + (int64_t)nen * te * 2;
         const int64_t per_node = 8 * (int64_t)record_len(op, damped != 0) + 8;
