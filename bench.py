@@ -376,8 +376,8 @@ def pmc_summary(trace_dir, fetch_dir, write_dir, commands):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-body batched vs plain comparison")
     ap.add_argument("--c5", action="store_true", help="also time the 256-body forward + adjoint + tangent graph")
