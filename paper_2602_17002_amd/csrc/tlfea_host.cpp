@@ -245,6 +245,12 @@ struct HostBuild {
     std::vector<ClassRange> classes;
 };
 
+// Largest entry count of a tile list (32-bit offsets); a test build lowers it.
+#ifndef TLFEA_OFFSET_LIMIT
+#define TLFEA_OFFSET_LIMIT INT32_MAX
+#endif
+constexpr int64_t kOffsetLimit = TLFEA_OFFSET_LIMIT;
+
 static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
 
 // Distinct nodes a tile may hold: at most kStagePerThread per thread, and
@@ -600,6 +606,16 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
         if (cr.tile_count > 0) hb.classes.push_back(cr);
     }
     if (hb.lnode_slot.size() & 1) hb.lnode_slot.push_back(0);   // whole 32-bit words
+    // The tile descriptors and the kernels address these lists with 32-bit
+    // offsets (about 200 million T10 elements per mesh); a larger problem is
+    // split over several meshes.
+    {
+        const size_t longest = std::max({hb.conn_local.size(), hb.lnode_slot.size(), hb.lnode_ptr.size(),
+                                         hb.lnode_gid.size(), hb.elem_uid.size()});
+        if (longest > (size_t)kOffsetLimit)
+            return fail(TLFEA_E_UNSUPPORTED, "mesh needs %zu tile-list entries, above the 32-bit offset limit %lld; "
+                        "split it over several meshes", longest, (long long)kOffsetLimit);
+    }
     // Nodes in exactly one tile are written by that tile.  Every other node
     // (shared, or touched by no element) gets the contiguous partial slots
     // [halo_ptr[h], halo_ptr[h+1]), one per tile that holds it, in tile
@@ -612,7 +628,8 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
             hb.halo_ptr.push_back((int32_t)hb.n_part);
             next_slot.push_back((int32_t)hb.n_part);
             hb.n_part += tile_count[g];
-            if (hb.n_part >= INT32_MAX) return fail(TLFEA_E_SHAPE, "too many shared-node partials");
+            if (hb.n_part >= kOffsetLimit)
+                return fail(TLFEA_E_UNSUPPORTED, "too many shared-node partials; split the mesh");
         }
     hb.halo_ptr.push_back((int32_t)hb.n_part);
     hb.lnode_dst.resize(hb.lnode_gid.size());

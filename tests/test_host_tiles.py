@@ -17,21 +17,26 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "host", "tiles_check.cpp")
 
 
-@pytest.fixture(scope="module")
-def harness(tmp_path_factory):
+def _compile(tmp_path_factory, name, defines=()):
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
-    exe = str(tmp_path_factory.mktemp("host") / "tiles_check")
+    exe = str(tmp_path_factory.mktemp("host") / name)
     cmd = [hipcc, "-O1", "-std=c++17", "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-w", "-I/opt/rocm/include",
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2602_17002_amd", "csrc"),
-           SRC, "-o", exe, "-L/opt/rocm/lib", "-lamdhip64"]
+           *defines, "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "paper_2602_17002_amd", "csrc"), SRC, "-o", exe, "-L/opt/rocm/lib",
+           "-lamdhip64"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     return exe
 
 
-def run(harness, tmp_path, X, blocks, flags=0):
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    return _compile(tmp_path_factory, "tiles_check")
+
+
+def _run_raw(harness, tmp_path, X, blocks, flags=0):
     path = tmp_path / "mesh.txt"
     with open(path, "w") as fh:
         fh.write(f"{X.shape[1]} {len(blocks)} {flags}\n")
@@ -40,7 +45,11 @@ def run(harness, tmp_path, X, blocks, flags=0):
             fh.write(f"{b.elem} {b.law} {int(b.damped)} {getattr(b, 'tile_elems', 0) or 0} {b.conn.shape[0]}\n")
             fh.write(" ".join(str(int(v)) for v in b.conn.ravel()) + "\n")
     env = dict(os.environ, LD_LIBRARY_PATH="/opt/rocm/lib:" + os.environ.get("LD_LIBRARY_PATH", ""))
-    r = subprocess.run([harness, str(path)], capture_output=True, text=True, env=env, timeout=120)
+    return subprocess.run([harness, str(path)], capture_output=True, text=True, env=env, timeout=120)
+
+
+def run(harness, tmp_path, X, blocks, flags=0):
+    r = _run_raw(harness, tmp_path, X, blocks, flags)
     out = r.stdout.strip().splitlines()
     assert r.returncode == 0 and out and out[-1].startswith("OK"), (r.stdout[-2000:], r.stderr[-2000:])
     return {k: int(v) for k, v in re.findall(r"(\w+) (\d+)", out[-1])}
@@ -75,3 +84,22 @@ def test_shared_nodes_between_blocks(harness, tmp_path):
     s = run(harness, tmp_path, X2, [b0, b1])
     # the listed nodes are the shared ones plus the untouched one (no partials)
     assert s["shared"] > 1 and s["partials"] >= 2 * (s["shared"] - 1)
+
+
+def test_offset_limit_rejects_oversized_mesh(tmp_path_factory, tmp_path):
+    # The tile lists use 32-bit offsets (about 200 million T10 elements per
+    # mesh).  A harness built with the limit lowered to 3000 entries shows
+    # that a mesh above it is refused with UNSUPPORTED instead of wrapping,
+    # and that one below it still builds.
+    exe = _compile(tmp_path_factory, "tiles_check_limit", ["-DTLFEA_OFFSET_LIMIT=3000"])
+    X, conn = synth.box_t10(4, 3, 3, size=(0.04, 0.03, 0.03))      # 216 elements, 2160 node slots
+    th = np.array([1.7e6, 0, 1.7e7, 0, 0])
+    small = synth.Block(synth.T10, synth.NH, conn, th)
+    small.tile_elems = 64
+    s = run(exe, tmp_path, X, [small])
+    assert s["tiles"] >= 4
+    X2, conn2 = synth.box_t10(6, 4, 3, size=(0.06, 0.04, 0.03))    # 432 elements, 4320 node slots
+    big = synth.Block(synth.T10, synth.NH, conn2, th)
+    big.tile_elems = 64
+    r = _run_raw(exe, tmp_path, X2, [big])
+    assert "FAIL build_tiles" in r.stdout and "32-bit offset limit" in r.stdout, (r.stdout[-2000:], r.stderr[-2000:])
