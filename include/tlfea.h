@@ -109,8 +109,10 @@ typedef struct {
  * TLFEA_E_SHAPE / TLFEA_E_REF_JACOBIAN / TLFEA_E_INVALID and leave *out NULL.
  * The mesh reorders elements along a Morton curve (unless TLFEA_KEEP_ORDER)
  * and cuts them into tiles; this never changes the caller-visible order of
- * theta / gtheta.  Ownership: the caller keeps its inputs; release the mesh
- * with tlfea_destroy_mesh.
+ * theta / gtheta.  The tile lists use 32-bit offsets: a mesh that would need
+ * more entries (about 200 million T10 elements) returns TLFEA_E_UNSUPPORTED,
+ * and such a problem is split over several meshes.  Ownership: the caller
+ * keeps its inputs; release the mesh with tlfea_destroy_mesh.
  */
 tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X_ref, int32_t n_blocks,
                                const tlfea_block *blocks, int32_t flags, tlfea_mesh **out);
