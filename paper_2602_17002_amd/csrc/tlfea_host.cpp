@@ -372,15 +372,24 @@ static void place_records(const uint16_t *conn, int n_elem, int n_node, int elem
 // Cut the elements `ids` (one block, Morton order) into tiles of at most te
 // elements and nl_max distinct nodes.  A tile grows from the first element
 // not yet taken (in Morton order) by repeatedly adding the element that has
-// the most nodes already in the tile (fewest new nodes), the earliest
-// reached one among equals (breadth first), so tiles are compact and share
-// few nodes with their neighbours.  Appends the tiles' element lists
+// the most nodes already in the tile (fewest new nodes), among equals the
+// one whose corner centroid is nearest the tile's, so tiles are compact and
+// share few nodes with their neighbours.  Appends the tiles' element lists
 // (positions in ids) to `out`.
-static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const std::vector<int64_t> &ids, int te, int nl_max,
-                       std::vector<std::vector<int64_t>> &out)
+static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const double *X, const std::vector<int64_t> &ids, int te,
+                       int nl_max, std::vector<std::vector<int64_t>> &out)
 {
-    const int nen = nen_of(B.elem);
+    const int nen = nen_of(B.elem), ncn = ncorner_of(B.elem);
     const int64_t ne = (int64_t)ids.size();
+    // corner centroids: among candidates that share equally many nodes with
+    // the tile, the one nearest the tile's centroid keeps the tile compact
+    std::vector<double> cen(3 * ne);
+    for (int64_t j = 0; j < ne; ++j)
+        for (int k = 0; k < 3; ++k) {
+            double s = 0;
+            for (int a = 0; a < ncn; ++a) s += X[k * n_nodes + B.conn[ids[j] * nen + a]];
+            cen[3 * j + k] = s / ncn;
+        }
     // node -> elements (positions in ids)
     std::vector<int64_t> nptr(n_nodes + 1, 0);
     for (int64_t j = 0; j < ne; ++j)
@@ -432,6 +441,7 @@ static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const std::vector<
             }
         };
         add(cursor);
+        double csum[3] = {cen[3 * cursor], cen[3 * cursor + 1], cen[3 * cursor + 2]};
         while ((int)members.size() < te) {
             int64_t best = -1;
             for (int sc = nen; sc >= 1 && best < 0; --sc) {
@@ -445,6 +455,22 @@ static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const std::vector<
                     best = j;
                     break;
                 }
+                if (best < 0) continue;
+                const double inv = 1.0 / (double)members.size();
+                double bd = 1e300;
+                for (size_t q = head[sc]; q < bk.size(); ++q) {
+                    const int64_t j = bk[q];
+                    if (taken[j] || stamp[j] != tile || score[j] != sc) continue;
+                    double d = 0;
+                    for (int k = 0; k < 3; ++k) {
+                        const double u = cen[3 * j + k] - csum[k] * inv;
+                        d += u * u;
+                    }
+                    if (d < bd) {
+                        bd = d;
+                        best = j;
+                    }
+                }
             }
             if (best < 0) {   // no element touches the tile: continue with the next in Morton order
                 int64_t c2 = cursor;
@@ -454,6 +480,7 @@ static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const std::vector<
             }
             if (nodes + fresh_of(best) > nl_max) break;
             add(best);
+            for (int k = 0; k < 3; ++k) csum[k] += cen[3 * best + k];
         }
         out.push_back(members);
     }
@@ -527,7 +554,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                     groups.push_back(std::move(g));
                 }
             } else {
-                grow_tiles(B, n_nodes, ord, te, nlmax, groups);
+                grow_tiles(B, n_nodes, X, ord, te, nlmax, groups);
             }
             for (const auto &grp : groups) {
                 nodes.clear();
