@@ -15,7 +15,9 @@
  *
  * Every element is processed in index order and every quadrature point in
  * table order, following the steps of the paper literally:
- *   U, N, Ndot gathered (Sec. 2.1, eq. r = N s; Sec. 6 isoparametric map)
+ *   U, N, Ndot gathered (Sec. 2.1, eq. r = N s; Sec. 6 isoparametric map),
+ *     positions relative to the element's first node (exact: the parent
+ *     gradients of the shape functions sum to zero, App. A)
  *   J = U G(xi_q), J_p = det J > 0, H = G J^{-1}          (Sec. 6)
  *   F = N H, Fdot = Ndot H                                  (Sec. 2.1)
  *   P = P_e(F) + F S_v(Edot)                                (Sec. 3.2, App. C)
@@ -384,13 +386,19 @@ static int qp_kinematics(const elem_t *E, int elem, int q, double H[][3], double
     return OR_OK;
 }
 
+/* The element's nodes.  Positions (U and N) are taken relative to the
+ * element's first node: the shape functions sum to one (App. A), so their
+ * parent gradients sum to zero and J = U G and F = N H are unchanged, while
+ * the products no longer cancel coordinates of order 1 m down to strains of
+ * order 1e-2 (about two digits on 1 cm elements).  The differences of nearby
+ * coordinates are themselves exact in FP64 (within a factor of two). */
 static void gather(elem_t *E, int64_t n_nodes, const int32_t *c, const double *X,
                    const double *x, const double *v)
 {
     for (int a = 0; a < E->nen; ++a)
         for (int i = 0; i < 3; ++i) {
-            E->U[i][a] = X[i*n_nodes + c[a]];
-            E->N[i][a] = x[i*n_nodes + c[a]];
+            E->U[i][a] = X[i*n_nodes + c[a]] - X[i*n_nodes + c[0]];
+            E->N[i][a] = x[i*n_nodes + c[a]] - x[i*n_nodes + c[0]];
             E->Nd[i][a] = v ? v[i*n_nodes + c[a]] : 0.0;
         }
 }
@@ -706,9 +714,9 @@ int oracle_element_tangent(int elem, int law, int damped, const double *theta,
     elem_t E;
     if (setup(&E, elem)) return OR_E_INVALID;
     for (int i = 0; i < 3; ++i)
-        for (int a = 0; a < E.nen; ++a) {
-            E.U[i][a] = Xe[i*E.nen + a];
-            E.N[i][a] = xe[i*E.nen + a];
+        for (int a = 0; a < E.nen; ++a) {   /* positions relative to node 0, as in gather() */
+            E.U[i][a] = Xe[i*E.nen + a] - Xe[i*E.nen];
+            E.N[i][a] = xe[i*E.nen + a] - xe[i*E.nen];
             E.Nd[i][a] = ve ? ve[i*E.nen + a] : 0.0;
         }
     mat_t m = mat_of(law, damped, theta, 1, 0);

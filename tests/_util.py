@@ -44,31 +44,9 @@ def sub_blocks(prob, nodes):
     return out, np.concatenate(cols)
 
 
-def centred(X, x, spans=None):
-    """Copies of X and x with each body moved so that its nodes' mean is at
-    the origin (spans: per-body (node_begin, node_end); None = one body).
-
-    The internal force and all its derivatives depend on X and x only
-    through differences of nodal values (the parent gradients of an element
-    sum to zero), so the oracle's exact result is unchanged.  Its FP64
-    rounding is not: a literal F = N H with coordinates of order 1 m on 1 cm
-    elements loses about two digits to cancellation, which on the
-    Neo-Hookean boxes amounts to a 1e-11 relative error, ten times the parity
-    bound.  The tests therefore evaluate the oracle on centred copies and
-    give the GPU the raw inputs; the GPU path is itself translation
-    invariant to rounding (it differences nodal positions per element)."""
-    X = np.array(X, dtype=np.float64, copy=True)
-    x = np.array(x, dtype=np.float64, copy=True)
-    for n0, n1 in (spans or [(0, X.shape[1])]):
-        if n1 > n0:
-            X[:, n0:n1] -= X[:, n0:n1].mean(axis=1, keepdims=True)
-            x[:, n0:n1] -= x[:, n0:n1].mean(axis=1, keepdims=True)
-    return X, x
-
-
 def patch(prob, node, arrays=("x", "v", "w", "dx", "dv")):
     """The elements incident to ``node`` as a small stand-alone problem with
-    local node numbering, centred on ``node`` (see ``centred``): everything the
+    local node numbering (the same coordinates, copied): everything the
     oracle needs to evaluate assembled values at that node.  Returns
     (X, blocks, {name: array}, local index of node, element columns)."""
     sub, cols = sub_blocks(prob, [node])
@@ -80,14 +58,12 @@ def patch(prob, node, arrays=("x", "v", "w", "dx", "dv")):
         nb = copy.copy(b)
         nb.conn = np.ascontiguousarray(loc[b.conn].astype(np.int32))
         out.append(nb)
-    X = prob.X[:, used] - prob.X[:, [node]]
+    X = prob.X[:, used]
     vals = {}
     for name in arrays:
         a = getattr(prob, name, None)
         if a is not None:
             vals[name] = np.ascontiguousarray(a[:, used])
-    if "x" in vals:
-        vals["x"] = vals["x"] - prob.x[:, [node]]
     return np.ascontiguousarray(X), out, vals, int(loc[node]), cols
 
 
