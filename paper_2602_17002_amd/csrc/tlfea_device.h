@@ -766,12 +766,13 @@ __device__ __forceinline__ const double *field_src(int f, const CallArgs &c)
 
 // Stage the tile's node records.  The host caps a tile at kStagePerThread x
 // (threads) nodes; every load of a thread is issued before its LDS stores.
-// Reference and current positions are staged relative to the tile's first
-// node: the kinematics only use differences of nodal positions (the parent
+// Reference and current positions are staged relative to the tile's
+// reference node (the one nearest the tile's centroid): the kinematics only
+// use differences of nodal positions (the parent
 // gradients of an element sum to zero), and coordinates of the size of a
 // tile instead of the size of the body keep the per-point gradient sums free
 // of cancellation.  The reference part is read contiguously from the mesh,
-// which stores it per tile node already relative to the tile's first node;
+// which stores it per tile node already relative to the tile's reference node;
 // the other fields are gathered from the caller's [3][n] arrays.  The mesh's
 // per-tile arrays are read once per call and are loaded non-temporally, which
 // leaves the L2 to the node data that neighbouring tiles share.  The nodes
@@ -787,7 +788,7 @@ __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMes
     const int32_t *gid = m.lnode_gid + t.node_begin;
     const uint16_t *lpos = m.lnode_pos + t.node_begin;
     const int64_t n = m.n_nodes;
-    const int g0 = gid[0];
+    const int g0 = gid[t.ref];
     int g[kStagePerThread], p[kStagePerThread];
 #pragma unroll
     for (int k = 0; k < kStagePerThread; ++k) {

@@ -210,7 +210,8 @@ static void block_order(const tlfea_block &b, int64_t n_nodes, const double *X, 
 // ------------------------------------------------------------------ validation
 
 // J_p = det(U G(xi_q)) > 0 at every quadrature point (Sec. 6).  Evaluated
-// with coordinates relative to the element's first node, as the kernels do.
+// with coordinates relative to the element's first node (exact differences,
+// no cancellation against the body's offset from the origin).
 static tlfea_status check_element(int elem, const int32_t *c, int64_t n_nodes, const double *X, int64_t e, int b)
 {
     const int nen = nen_of(elem), nq = nq_of(elem);
@@ -575,7 +576,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                 t.ptr_begin = (int32_t)hb.lnode_ptr.size();
                 t.conn_begin = (int32_t)hb.conn_local.size();
                 t.block = b;
-                t.pad = 0;
+                t.ref = 0;
                 if (t.n_node > nlmax || t.n_node > kStagePerThread * te)
                     return fail(TLFEA_E_UNSUPPORTED, "tile with %d nodes exceeds the limit %d", t.n_node, nlmax);
                 for (size_t l = 0; l < nodes.size(); ++l) {
@@ -753,12 +754,31 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
     m->tile_nodes = hb.lnode_gid;
     m->n_tiles = (int64_t)hb.tiles.size();
     DevMesh &d = m->dm;
-    // reference coordinates per tile node, relative to the tile's first node
-    // (the same differences the kernels would form from X)
+    // Reference coordinates per tile node, relative to the tile's node
+    // nearest the centroid of its nodes; the kernels take current positions
+    // relative to the same node.  The differences of nearby coordinates are
+    // exact, and the smaller they are, the less the sums over an element's
+    // nodes (F = N H, J = U G) cancel.
     const int64_t n_tnode = (int64_t)hb.lnode_gid.size();
     std::vector<double> Xt(3 * (size_t)n_tnode);
-    for (const TileDesc &t : hb.tiles) {
-        const int32_t g0 = hb.lnode_gid[t.node_begin];
+    for (TileDesc &t : hb.tiles) {
+        double cen[3] = {0, 0, 0};
+        for (int l = 0; l < t.n_node; ++l)
+            for (int c = 0; c < 3; ++c) cen[c] += X[c * n_nodes + hb.lnode_gid[t.node_begin + l]];
+        double best = 1e300;
+        t.ref = 0;
+        for (int l = 0; l < t.n_node; ++l) {
+            double d = 0;
+            for (int c = 0; c < 3; ++c) {
+                const double u = X[c * n_nodes + hb.lnode_gid[t.node_begin + l]] - cen[c] / t.n_node;
+                d += u * u;
+            }
+            if (d < best) {
+                best = d;
+                t.ref = l;
+            }
+        }
+        const int32_t g0 = hb.lnode_gid[t.node_begin + t.ref];
         for (int l = 0; l < t.n_node; ++l) {
             const int32_t g = hb.lnode_gid[t.node_begin + l];
             for (int c = 0; c < 3; ++c)

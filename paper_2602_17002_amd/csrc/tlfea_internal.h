@@ -15,7 +15,8 @@ struct TileDesc {
     int32_t ptr_begin;    // first entry of this tile's lnode_ptr (n_node + 1 entries)
     int32_t conn_begin;   // first entry of this tile's conn_local ([nen][te])
     int32_t block;        // owning block
-    int32_t pad;
+    int32_t ref;          // local index of the node positions are taken relative to
+                          // (the tile's node nearest the centroid of its nodes)
 };
 
 // Node records a thread stages at most: a tile holds at most this many
@@ -39,7 +40,7 @@ struct DevMesh {
     const int32_t *elem_uid;      // caller's element id of each internal element
     const BlockDesc *blocks;
     const double *Xt;             // [3][n_tnode] reference coordinates of every tile node,
-                                  // relative to its tile's first node
+                                  // relative to its tile's reference node (TileDesc::ref)
     const int32_t *halo_gid;      // nodes summed from partials (and nodes no element touches)
     const int32_t *halo_ptr;      // [n_halo + 1]: node h owns partial slots [halo_ptr[h], halo_ptr[h+1])
     double *part;                 // [6][n_part] partial node sums (two fields x three components)
