@@ -397,3 +397,35 @@ def test_inverted_point_count(elem):
     assert 0 < n < n_qp
     assert n == nb
     assert mn > 1e-3 and abs(mn - mnb) < 1e-9
+
+
+# ---------------------------------------------------------- position offsets
+
+@pytest.mark.parametrize("elem", [O.T10, O.H8])
+def test_results_depend_only_on_position_differences(elem):
+    # The kinematics use positions only through differences of an element's
+    # nodes (the parent gradients sum to zero, App. A), and the oracle forms
+    # those differences before any product.  With coordinates on a grid of
+    # 2^-40 m and a translation by powers of two, every translated
+    # coordinate is exact and so is every difference: all outputs must be
+    # bitwise equal.  A literal F = N H on coordinates of order 1000 m would
+    # lose about eleven digits here.
+    rng = np.random.default_rng(41)
+    q = 2.0 ** -40
+    X, conn = small_mesh(elem, n=(3, 2, 2), size=(0.03, 0.02, 0.02))
+    X = np.round(X / q) * q
+    x = np.round(deformed(X, rng, 0.02) / q) * q
+    v = rng.normal(0, 0.1, X.shape)
+    w = rng.standard_normal(X.shape)
+    dx = rng.standard_normal(X.shape) * 1e-3
+    T = np.array([[1024.0], [-2048.0], [512.0]])
+    assert np.array_equal((X + T) - T, X) and np.array_equal((x + T) - T, x)
+    for law, th in LAWS.values():
+        b = [blk(elem, law, conn, th, True)]
+        for fn in (lambda XX, xx: O.internal_force(XX, b, xx, v),
+                   lambda XX, xx: O.vjp(XX, b, xx, v, w),
+                   lambda XX, xx: O.jvp(XX, b, xx, v, dx, None),
+                   lambda XX, xx: O.count_inverted(XX, b, xx)):
+            a0, a1 = fn(X, x), fn(X + T, x + T)
+            for u, t in zip(a0 if isinstance(a0, tuple) else (a0,), a1 if isinstance(a1, tuple) else (a1,)):
+                assert np.array_equal(np.asarray(u), np.asarray(t))
