@@ -179,12 +179,15 @@ static void block_order(const tlfea_block &b, int64_t n_nodes, const double *X, 
     ord.resize(ne);
     for (int64_t e = 0; e < ne; ++e) ord[e] = e;
     if (keep || ne < 2) return;
+    // corner centroids relative to the block's first node: the order then
+    // does not depend on where the body sits
     std::vector<double> cen(3 * ne);
+    const int32_t g0 = b.conn[0];
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t e = 0; e < ne; ++e)
         for (int k = 0; k < 3; ++k) {
             double s = 0;
-            for (int a = 0; a < nc; ++a) s += X[k * n_nodes + b.conn[e * nen + a]];
+            for (int a = 0; a < nc; ++a) s += X[k * n_nodes + b.conn[e * nen + a]] - X[k * n_nodes + g0];
             s /= nc;
             cen[3 * e + k] = s;
             lo[k] = std::min(lo[k], s);
@@ -382,13 +385,16 @@ static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const double *X, c
 {
     const int nen = nen_of(B.elem), ncn = ncorner_of(B.elem);
     const int64_t ne = (int64_t)ids.size();
-    // corner centroids: among candidates that share equally many nodes with
-    // the tile, the one nearest the tile's centroid keeps the tile compact
+    if (ne == 0) return;
+    // corner centroids (relative to the block's first node): among
+    // candidates that share equally many nodes with the tile, the one
+    // nearest the tile's centroid keeps the tile compact
     std::vector<double> cen(3 * ne);
+    const int32_t g0 = B.conn[0];
     for (int64_t j = 0; j < ne; ++j)
         for (int k = 0; k < 3; ++k) {
             double s = 0;
-            for (int a = 0; a < ncn; ++a) s += X[k * n_nodes + B.conn[ids[j] * nen + a]];
+            for (int a = 0; a < ncn; ++a) s += X[k * n_nodes + B.conn[ids[j] * nen + a]] - X[k * n_nodes + g0];
             cen[3 * j + k] = s / ncn;
         }
     // node -> elements (positions in ids)
@@ -762,15 +768,19 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
     const int64_t n_tnode = (int64_t)hb.lnode_gid.size();
     std::vector<double> Xt(3 * (size_t)n_tnode);
     for (TileDesc &t : hb.tiles) {
+        // centroid and distances relative to the first node, so that the
+        // choice does not depend on where the body sits
+        const int32_t gf = hb.lnode_gid[t.node_begin];
+        auto rel = [&](int l, int c) { return X[c * n_nodes + hb.lnode_gid[t.node_begin + l]] - X[c * n_nodes + gf]; };
         double cen[3] = {0, 0, 0};
         for (int l = 0; l < t.n_node; ++l)
-            for (int c = 0; c < 3; ++c) cen[c] += X[c * n_nodes + hb.lnode_gid[t.node_begin + l]];
+            for (int c = 0; c < 3; ++c) cen[c] += rel(l, c);
         double best = 1e300;
         t.ref = 0;
         for (int l = 0; l < t.n_node; ++l) {
             double d = 0;
             for (int c = 0; c < 3; ++c) {
-                const double u = X[c * n_nodes + hb.lnode_gid[t.node_begin + l]] - cen[c] / t.n_node;
+                const double u = rel(l, c) - cen[c] / t.n_node;
                 d += u * u;
             }
             if (d < best) {

@@ -153,6 +153,34 @@ def test_every_operation_at_every_tile_size(elem, tile):
     assert rel(df, O.jvp(*oc(p), p.v, p.dx, p.dv)) <= TOL
 
 
+@pytest.mark.parametrize("elem", [synth.T10, synth.H8], ids=["T10", "H8"])
+def test_outputs_unchanged_by_exact_translation(elem):
+    # Positions enter only through differences against each tile's
+    # reference node; with coordinates on a 2^-40 m grid and an offset by
+    # powers of two every translated coordinate and every difference is
+    # exact, so the outputs must not change by a single bit.
+    p = make_problem(elem, "NH", True, n=(8, 5, 4), per_elem=True, seed=50)
+    q = 2.0 ** -40
+    X, x = np.round(p.X / q) * q, np.round(p.x / q) * q
+    T = np.array([[1024.0], [-2048.0], [512.0]])
+    assert np.array_equal((X + T) - T, X) and np.array_equal((x + T) - T, x)
+    say("translation", p.name)
+    th = to_dev(p.theta_all())
+    outs = []
+    for XX, xx in ((X, x), (X + T, x + T)):
+        pp = copy.copy(p)
+        pp.X = np.ascontiguousarray(XX)
+        m = mesh_of(pp)
+        xd, vd = to_dev(xx), to_dev(p.v)
+        f = to_host(m.internal_force(xd, vd, th))
+        gx, gv, gt = (to_host(a) for a in m.vjp(xd, vd, to_dev(p.w), th))
+        df = to_host(m.jvp(xd, vd, to_dev(p.dx), to_dev(p.dv), th))
+        outs.append((f, gx, gv, gt, df))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    assert rel(outs[0][0], O.internal_force(X, p.blocks, x, p.v)) <= TOL
+
+
 def test_c1_cantilever_all_outputs_and_repeatability():
     p = synth.config_c1()
     say("C1 cantilever", p.n_elem)
