@@ -19,7 +19,8 @@ one plain mesh per body launched back to back on one stream.
 Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 
 --pmc-summary DIR writes the rocprofv3 summaries under profiles/ from the
-output folders of a kernel-trace run and two counter runs.
+output folders of a kernel-trace run and two counter runs; --sq-summary
+writes the SQ counter summary from counter runs of the same command.
 """
 from __future__ import annotations
 
@@ -377,6 +378,38 @@ def pmc_summary(trace_dir, fetch_dir, write_dir, commands):
 
 # ---------------------------------------------------------------- main
 
+def sq_summary(dirs, commands):
+    """Write profiles/sq_counters_c2_fwd_vjp.md from rocprofv3 --pmc runs of
+    SQ counters over the bench: the median per dispatch of every counter for
+    the tile kernels, the LDS bank-conflict share of LDS-active cycles, and
+    the FP64 flops the hardware executed per element."""
+    os.makedirs(PROFILES, exist_ok=True)
+    acc = {}
+    for d in dirs:
+        for r in _csv_rows(os.path.join(d, "**", "*counter_collection.csv")):
+            if "tlfea::k_" not in r["Kernel_Name"] or "k_halo" in r["Kernel_Name"]:
+                continue
+            acc.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    lines = ["# SQ counters per dispatch: C2 forward + adjoint (1,020,000 T10, Neo-Hookean + Kelvin-Voigt)", ""]
+    for k in sorted(commands):
+        lines += [f"Command {k}: `{commands[k]}`", ""]
+    lines += ["Medians over the dispatches of each kernel. `bank-conflict share` = SQ_LDS_BANK_CONFLICT / "
+              "SQ_LDS_IDX_ACTIVE; `FP64 flop / element` = SQ_INSTS_VALU_FLOPS_FP64 x 64 / 1,020,000.", ""]
+    for k in sorted(acc):
+        c = {n: float(np.median(v)) for n, v in acc[k].items()}
+        lines += [f"## `{k[:90]}`", "", "| counter | median per dispatch |", "|---|---|"]
+        lines += [f"| {n} | {c[n]:.4g} |" for n in sorted(c)]
+        if c.get("SQ_LDS_IDX_ACTIVE"):
+            lines.append(f"| bank-conflict share | {c.get('SQ_LDS_BANK_CONFLICT', 0.0) / c['SQ_LDS_IDX_ACTIVE']:.3f} |")
+        if "SQ_INSTS_VALU_FLOPS_FP64" in c:
+            lines.append(f"| FP64 flop / element | {c['SQ_INSTS_VALU_FLOPS_FP64'] * 64 / 1020000:.0f} |")
+        lines.append("")
+    lines.append(f"SOURCE_SHA256 {source_hash()}")
+    with open(os.path.join(PROFILES, "sq_counters_c2_fwd_vjp.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines[-3:]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,8 +425,14 @@ def main():
                     help="also run one device-to-device copy of this many MiB (a kernel of known "
                          "traffic, used to scale the HBM byte counters of a profiler run)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"))
-    ap.add_argument("--commands", default="{}", help="JSON: the profiler command lines (for --pmc-summary)")
+    ap.add_argument("--sq-summary", nargs="+", metavar="PMC_DIR",
+                    help="write profiles/sq_counters_c2_fwd_vjp.md from rocprofv3 --pmc runs of SQ counters")
+    ap.add_argument("--commands", default="{}",
+                    help="JSON: the profiler command lines (for --pmc-summary / --sq-summary)")
     args = ap.parse_args()
+    if args.sq_summary:
+        sq_summary(args.sq_summary, json.loads(args.commands))
+        return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, json.loads(args.commands))
         return
