@@ -493,6 +493,54 @@ static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const double *X, c
     }
 }
 
+// Lane order within a tile.  A gather of node slot a by 16 consecutive lanes
+// costs a cycle per distinct address in the busiest bank pair, and lanes
+// that read the same node share one address.  The tile's elements (Morton
+// positions in ord) are therefore dealt out in groups of 16: each group
+// starts with the first element left and adds, one at a time, the element
+// whose nodes coincide with the group's at the most slots (the first such
+// element in Morton order among equals).
+static void order_lanes(const tlfea_block &B, const std::vector<int64_t> &ord, std::vector<int64_t> &grp)
+{
+    constexpr int kGroup = 16;
+    const int nen = nen_of(B.elem);
+    std::sort(grp.begin(), grp.end());
+    const int ng = (int)grp.size();
+    // (node, slot) -> elements of the tile with that node at that slot
+    std::vector<std::pair<int64_t, int>> key;
+    key.reserve((size_t)ng * nen);
+    for (int j = 0; j < ng; ++j)
+        for (int a = 0; a < nen; ++a) key.push_back({(int64_t)B.conn[ord[grp[j]] * nen + a] * nen + a, j});
+    std::sort(key.begin(), key.end());
+    std::vector<char> used(ng, 0);
+    std::vector<int> score(ng);
+    std::vector<int64_t> seen, out;
+    out.reserve(ng);
+    int first = 0;
+    while ((int)out.size() < ng) {
+        std::fill(score.begin(), score.end(), 0);
+        seen.clear();
+        for (int k = 0; k < kGroup && (int)out.size() < ng; ++k) {
+            while (used[first]) ++first;
+            int best = first;
+            for (int j = first + 1; j < ng; ++j)
+                if (!used[j] && score[j] > score[best]) best = j;
+            used[best] = 1;
+            out.push_back(grp[best]);
+            // every (node, slot) new to the group raises the score of the
+            // elements that share it
+            for (int a = 0; a < nen; ++a) {
+                const int64_t kk = (int64_t)B.conn[ord[grp[best]] * nen + a] * nen + a;
+                if (std::find(seen.begin(), seen.end(), kk) != seen.end()) continue;
+                seen.push_back(kk);
+                auto lo = std::lower_bound(key.begin(), key.end(), std::make_pair(kk, -1));
+                for (auto it = lo; it != key.end() && it->first == kk; ++it) score[it->second]++;
+            }
+        }
+    }
+    grp.swap(out);
+}
+
 static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, const tlfea_block *blocks, int flags,
                                 const std::vector<int> &te_of_block, int64_t lds_dev, HostBuild &hb)
 {
@@ -563,6 +611,8 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
             } else {
                 grow_tiles(B, n_nodes, X, ord, te, nlmax, groups);
             }
+            if (!(flags & TLFEA_KEEP_ORDER))
+                for (auto &grp : groups) order_lanes(B, ord, grp);
             for (const auto &grp : groups) {
                 nodes.clear();
                 for (int64_t pos : grp) {
