@@ -70,7 +70,7 @@ enum { TLFEA_NPAR = 5 };                         /* parameter rows          */
 enum {
     TLFEA_PLAIN = 0,
     TLFEA_BATCHED = 1,      /* replay each call's launches as one hipGraph    */
-    TLFEA_AUTOTUNE = 2,     /* time candidate tile sizes at creation          */
+    TLFEA_AUTOTUNE = 2,     /* time tile sizes at creation, keep one per type */
     TLFEA_KEEP_ORDER = 4    /* keep the caller's element order (no reorder)  */
 };
 

@@ -1119,12 +1119,13 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
     std::vector<int> te(n_blocks);
     for (int b = 0; b < n_blocks; ++b) te[b] = blocks[b].tile_elems ? blocks[b].tile_elems : default_te(blocks[b].elem);
     if (!(flags & TLFEA_AUTOTUNE)) return create_with(n_nodes, X, n_blocks, blocks, flags, te, out);
-    // Autotune: per (element, law, damping) class, the tile size with the
-    // smallest forward + adjoint + tangent time over the class's own tiles;
-    // blocks that fix tile_elems keep it.
+    // Autotune: per element type, the tile size with the smallest forward +
+    // adjoint + tangent time summed over the classes of that type (one size
+    // per type, as tlfea_get_mesh_info reports it); blocks that fix
+    // tile_elems keep it.
     const int cand[4] = {64, 128, 192, 256};
-    std::vector<double> best_t(n_blocks, 1e300);
-    std::vector<int> best_te = te;
+    double best_t[2] = {1e300, 1e300};
+    int best_c[2] = {default_te(kT10), default_te(kH8)};
     for (int ci = 0; ci < 4; ++ci) {
         std::vector<int> tc(n_blocks);
         for (int b = 0; b < n_blocks; ++b) tc[b] = blocks[b].tile_elems ? blocks[b].tile_elems : cand[ci];
@@ -1137,19 +1138,18 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
             tlfea_destroy_mesh(m);
             return st;
         }
-        for (int b = 0; b < n_blocks; ++b) {
-            if (blocks[b].tile_elems) continue;
-            for (size_t k = 0; k < m->classes.size(); ++k) {
-                const ClassRange &cr = m->classes[k];
-                if (cr.elem == blocks[b].elem && cr.law == blocks[b].law && cr.damped == (blocks[b].damped ? 1 : 0) &&
-                    t[k] < best_t[b]) {
-                    best_t[b] = t[k];
-                    best_te[b] = cand[ci];
-                }
+        double sum[2] = {0.0, 0.0};
+        for (size_t k = 0; k < m->classes.size(); ++k) sum[m->classes[k].elem] += t[k];
+        for (int e = 0; e < 2; ++e)
+            if (sum[e] < best_t[e]) {
+                best_t[e] = sum[e];
+                best_c[e] = cand[ci];
             }
-        }
         tlfea_destroy_mesh(m);
     }
+    std::vector<int> best_te = te;
+    for (int b = 0; b < n_blocks; ++b)
+        if (!blocks[b].tile_elems) best_te[b] = best_c[blocks[b].elem];
     return create_with(n_nodes, X, n_blocks, blocks, flags, best_te, out);
 }
 
