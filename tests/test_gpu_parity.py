@@ -492,6 +492,7 @@ def test_full_size_multibody_sampled_against_oracle(cfg):
     p = synth.config_c3() if cfg == "C3" else synth.config_c5()
     say("full-size multibody", cfg, len(p.blocks), "bodies", p.n_elem, "elements")
     m = mesh_of(p, flags=BATCHED | (AUTOTUNE if cfg == "C5" else 0))
+    info = m.info()
     e0 = np.concatenate([[0], np.cumsum([b.conn.shape[0] for b in p.blocks])])
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
@@ -539,6 +540,18 @@ def test_full_size_multibody_sampled_against_oracle(cfg):
                 else:
                     assert np.all(gtb[r] == 0), (bi, r)
             assert rel(df[:, n0:n1], O.jvp(Xc, blk, xc, None, p.dx[:, n0:n1])) <= TOL, bi
+            # a plain mesh of the body alone, with the tile size the
+            # autotuner chose for its element type, sums in the same order
+            bb = copy.copy(blk[0])
+            bb.tile_elems = info["tile_elems_t10" if bb.elem == synth.T10 else "tile_elems_h8"]
+            from paper_2602_17002_amd import Mesh
+            mb = Mesh(Xc, [bb])
+            xb = to_dev(xc)
+            gxb, _, gtb = mb.vjp(xb, None, to_dev(p.w[:, n0:n1]), want_v=False)
+            assert np.array_equal(to_host(mb.internal_force(xb)), f[:, n0:n1]), bi
+            assert np.array_equal(to_host(gxb), gx[:, n0:n1]), bi
+            assert np.array_equal(to_host(gtb), gt[:, e0[bi]:e0[bi + 1]]), bi
+            assert np.array_equal(to_host(mb.jvp(xb, None, to_dev(p.dx[:, n0:n1]))), df[:, n0:n1]), bi
 
 
 def test_c4_finite_differences_and_adjoint_consistency():
