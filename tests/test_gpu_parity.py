@@ -153,6 +153,40 @@ def test_every_operation_at_every_tile_size(elem, tile):
     assert rel(df, O.jvp(*oc(p), p.v, p.dx, p.dv)) <= TOL
 
 
+@pytest.mark.parametrize("law", ["SVK", "NH", "MR"])
+@pytest.mark.parametrize("elem", [synth.T10, synth.H8], ids=["T10", "H8"])
+def test_large_deformation(elem, law):
+    # Strains up to 40 % (peak displacement gradient 0.4, with a volumetric
+    # part) under a rigid rotation and fast velocities: every output against
+    # the oracle, with every |det F| checked to stay clear of zero.
+    rng = np.random.default_rng(60)
+    lid, th = LAWS[law]
+    n = (6, 4, 3)
+    X, conn = (synth.box_t10 if elem == synth.T10 else synth.box_h8)(*n, size=tuple(0.02 * k for k in n))
+    x = synth.sinusoidal_state(X, 0.4, rng)
+    v = rng.normal(0, 5.0, X.shape)
+    b = synth.Block(elem, lid, conn, th.copy(), damped=True)
+    b.theta_e = th[:, None] * rng.uniform(0.5, 2.0, (5, conn.shape[0]))
+    p = synth.Problem(f"large-{synth.ELEM_NAMES[elem]}-{law}", X, x, v, [b], cell=0.02)
+    ninv, min_det = O.count_inverted(p.X, p.blocks, p.x)
+    assert ninv == 0 and min_det > 0.2, (ninv, min_det)
+    w, dx, dv = rng.standard_normal(X.shape), rng.standard_normal(X.shape) * 0.02, rng.standard_normal(X.shape)
+    say("large deformation", p.name, "min det F", min_det)
+    m = mesh_of(p)
+    th_d = to_dev(p.theta_all())
+    xd, vd = to_dev(x), to_dev(v)
+    assert rel(to_host(m.internal_force(xd, vd, th_d)), O.internal_force(X, p.blocks, x, v)) <= TOL
+    gx, gv, gt = m.vjp(xd, vd, to_dev(w), th_d)
+    rx, rv, rt = O.vjp(X, p.blocks, x, v, w)
+    assert rel(to_host(gx), rx) <= TOL and rel(to_host(gv), rv) <= TOL
+    gt = to_host(gt)
+    for r in range(5):
+        if np.abs(rt[r]).max() > 0:
+            assert rel(gt[r], rt[r]) <= TOL, r
+    df = to_host(m.jvp(xd, vd, to_dev(dx), to_dev(dv), th_d))
+    assert rel(df, O.jvp(X, p.blocks, x, v, dx, dv)) <= TOL
+
+
 @pytest.mark.parametrize("elem", [synth.T10, synth.H8], ids=["T10", "H8"])
 def test_outputs_unchanged_by_exact_translation(elem):
     # Positions enter only through differences against each tile's
