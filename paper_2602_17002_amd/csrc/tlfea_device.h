@@ -991,7 +991,7 @@ __device__ __forceinline__ void zero_nodes(const DevMesh &m, const TileDesc &t, 
 #define TLFEA_MAX_TE 256
 
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LAW == 1 ? 2 : 3))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpFwd, ELEM, LAW, DAMPED)))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpFwd, DAMPED>;
@@ -1026,7 +1026,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LA
 // needs more than that and spilled 488 B per lane there, runs at one wave
 // per SIMD with its whole state in registers (24 % faster).
 template <int ELEM, int LAW, bool DAMPED, bool WANT_GT>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LAW == 1 && DAMPED ? 1 : 2))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpVjp, ELEM, LAW, DAMPED)))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpVjp, DAMPED>;
@@ -1077,7 +1077,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(LA
 // wave and 512 registers, which ran about 20 % slower than two waves with a
 // small spill.
 template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(2))) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpJvp, ELEM, LAW, DAMPED)))) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
     using R = Rec<kOpJvp, DAMPED>;

@@ -262,17 +262,18 @@ static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
 // within its LDS budget.
 // LDS budget of one workgroup of an operation: the device's per-workgroup
 // limit, and at most the share of a 160 KiB compute-unit LDS that lets as
-// many workgroups be resident as the kernel's register use allows (three
-// waves per SIMD for the forward, two for the adjoint and the tangent; a
-// workgroup of te elements has te / 64 waves).
-static int64_t lds_budget(int op, int te, int64_t lds_dev)
+// many workgroups be resident as the kernel's register use allows (a
+// workgroup of te elements has te / 64 waves).  The forward is budgeted for
+// three waves per SIMD and the other operations for their own count, at
+// least two.
+static int64_t lds_budget(int op, int elem, int law, int damped, int te, int64_t lds_dev)
 {
-    const int64_t waves_per_cu = op == kOpFwd ? 12 : 8;
+    const int64_t waves_per_cu = op == kOpFwd ? 12 : 4 * std::max(2, waves_per_simd(op, elem, law, damped != 0));
     const int64_t wgs = std::max<int64_t>(1, waves_per_cu * 64 / te);
     return std::min<int64_t>(lds_dev, 163840 / wgs);
 }
 
-static int nl_limit(int elem, int te, int damped, int64_t lds_dev)
+static int nl_limit(int elem, int law, int te, int damped, int64_t lds_dev)
 {
     const int nen = nen_of(elem);
     int64_t nl = (int64_t)kStagePerThread * te;
@@ -285,7 +286,7 @@ static int nl_limit(int elem, int te, int damped, int64_t lds_dev)
     for (int op = kOpFwd; op <= kOpJvp; ++op) {
         const int64_t fixed = 4 + (int64_t)nen * te * 2;
         const int64_t per_node = 8 * (int64_t)record_len(op, damped != 0) + 8;
-        nl = std::min(nl, (lds_budget(op, te, lds_dev) - fixed) / per_node);
+        nl = std::min(nl, (lds_budget(op, elem, law, damped, te, lds_dev) - fixed) / per_node);
     }
     return (int)nl;
 }
@@ -304,7 +305,7 @@ static size_t lds_bytes(const ClassRange &c, int op, int nc)
 static int comps_per_round(const ClassRange &c, int op, int64_t lds_dev)
 {
     for (int nc = 3; nc > 1; --nc)
-        if ((int64_t)lds_bytes(c, op, nc) <= lds_budget(op, c.te, lds_dev)) return nc;
+        if ((int64_t)lds_bytes(c, op, nc) <= lds_budget(op, c.elem, c.law, c.damped, c.te, lds_dev)) return nc;
     return 1;
 }
 
@@ -579,7 +580,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
     for (size_t k = 0; k < keys.size(); ++k) {
         ClassRange cr{keys[k].elem, keys[k].law, keys[k].damped, keys[k].te, (int)hb.tiles.size(), 0, 0, {1, 1, 1}};
         const int te = keys[k].te, nen = nen_of(keys[k].elem);
-        const int nlmax = nl_limit(keys[k].elem, te, keys[k].damped, lds_dev);
+        const int nlmax = nl_limit(keys[k].elem, keys[k].law, te, keys[k].damped, lds_dev);
         if (nlmax < nen || (int64_t)nen * te * (int64_t)sizeof(double) > 65536)
             return fail(TLFEA_E_UNSUPPORTED, "tile of %d elements does not fit the LDS of one workgroup", te);
         for (int b = 0; b < n_blocks; ++b) {

@@ -56,6 +56,25 @@ struct CallArgs {
 
 enum { kOpFwd = 0, kOpVjp = 1, kOpJvp = 2 };
 
+// Waves per SIMD each tile kernel is compiled for (its register budget:
+// 512 / waves registers per lane), shared by the kernels' attributes and the
+// host's LDS budget.  Measured per instantiation: three waves where the
+// kernel then still fits its registers without spilling (the undamped
+// Saint Venant-Kirchhoff and Neo-Hookean H8 adjoint and tangent, the
+// undamped Saint Venant-Kirchhoff T10 tangent: 8-14 % faster), two where
+// spills would cost more than the extra wave gains (Mooney-Rivlin, the
+// damped adjoint's two sets of accumulators, the other T10 cases), and the
+// damped Mooney-Rivlin adjoint a whole SIMD's registers.  Laws: 0 SVK,
+// 1 Mooney-Rivlin, 2 Neo-Hookean; element 1 is H8.
+constexpr int waves_per_simd(int op, int elem, int law, bool damped)
+{
+    if (op == kOpFwd) return law == 1 ? 2 : 3;
+    if (op == kOpVjp && law == 1 && damped) return 1;
+    if (damped || law == 1) return 2;
+    if (elem == 1) return 3;
+    return (op == kOpJvp && law == 0) ? 3 : 2;
+}
+
 // Doubles a node record of an operation holds: X and x, plus w (adjoint) or
 // dx (tangent), plus v when damped, plus dv for the damped tangent.
 constexpr int record_fields_len(int op, bool damped)
