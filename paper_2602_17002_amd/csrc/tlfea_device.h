@@ -990,6 +990,8 @@ __device__ __forceinline__ void zero_nodes(const DevMesh &m, const TileDesc &t, 
 
 #define TLFEA_MAX_TE 256
 
+
+
 template <int ELEM, int LAW, bool DAMPED>
 __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpFwd, ELEM, LAW, DAMPED)))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
@@ -1159,20 +1161,24 @@ hipError_t launch_inverted_class(int te, int n_tiles, size_t lds, hipStream_t s,
     return hipGetLastError();
 }
 
-template <int OP, int ELEM, int LAW, bool DAMPED>
+template <int OP, int ELEM, int LAW, bool DAMPED, int GT>
 hipError_t launch_one(dim3 grid, int te, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c, int tile0,
                       int ntile, int nl, int nc)
 {
     if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     else if constexpr (OP == kOpVjp) {
-        if (c.gtheta) k_vjp<ELEM, LAW, DAMPED, true><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
-        else k_vjp<ELEM, LAW, DAMPED, false><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+        // one adjoint translation unit per gtheta choice (each with the
+        // instruction scheduler that suits it); the host picks the unit
+        if ((c.gtheta != nullptr) != (GT != 0)) return hipErrorInvalidValue;
+        k_vjp<ELEM, LAW, DAMPED, GT != 0><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     }
     else k_jvp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     return hipGetLastError();
 }
 
-template <int OP, int ELEM>
+// GT: which adjoint a unit instantiates (part of the template arguments, so
+// that the two adjoint units' launchers are distinct functions)
+template <int OP, int ELEM, int GT>
 hipError_t launch_class(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m,
                         const CallArgs &c, int tile0, int nl, int nc)
 {
@@ -1180,12 +1186,12 @@ hipError_t launch_class(int law, int damped, int te, int n_tiles, size_t lds, hi
     if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
     switch (law * 2 + (damped ? 1 : 0)) {
-    case 0: return launch_one<OP, ELEM, 0, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 1: return launch_one<OP, ELEM, 0, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 2: return launch_one<OP, ELEM, 1, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 3: return launch_one<OP, ELEM, 1, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 4: return launch_one<OP, ELEM, 2, false>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 5: return launch_one<OP, ELEM, 2, true>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 0: return launch_one<OP, ELEM, 0, false, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 1: return launch_one<OP, ELEM, 0, true, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 2: return launch_one<OP, ELEM, 1, false, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 3: return launch_one<OP, ELEM, 1, true, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 4: return launch_one<OP, ELEM, 2, false, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 5: return launch_one<OP, ELEM, 2, true, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
     default: return hipErrorInvalidValue;
     }
 }

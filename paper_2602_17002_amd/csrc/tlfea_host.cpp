@@ -23,10 +23,12 @@ namespace tlfea {
     hipError_t launch_tiles_e##e##_o##o(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, \
                                         const DevMesh &m, const CallArgs &c, int tile0, int nl, int nc);
 TLFEA_DECL(0, 0)
-TLFEA_DECL(0, 1)
+TLFEA_DECL(0, 1_g0)
+TLFEA_DECL(0, 1_g1)
 TLFEA_DECL(0, 2)
 TLFEA_DECL(1, 0)
-TLFEA_DECL(1, 1)
+TLFEA_DECL(1, 1_g0)
+TLFEA_DECL(1, 1_g1)
 TLFEA_DECL(1, 2)
 #undef TLFEA_DECL
 hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1);
@@ -41,10 +43,13 @@ static hipError_t launch_tiles(int elem, int law, int damped, int te, int op, in
 {
     typedef hipError_t (*fn_t)(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int,
                                int);
-    static const fn_t table[2][3] = {{launch_tiles_e0_o0, launch_tiles_e0_o1, launch_tiles_e0_o2},
-                                     {launch_tiles_e1_o0, launch_tiles_e1_o1, launch_tiles_e1_o2}};
+    // the adjoint has one unit without and one with the parameter gradients
+    static const fn_t table[2][4] = {
+        {launch_tiles_e0_o0, launch_tiles_e0_o1_g0, launch_tiles_e0_o2, launch_tiles_e0_o1_g1},
+        {launch_tiles_e1_o0, launch_tiles_e1_o1_g0, launch_tiles_e1_o2, launch_tiles_e1_o1_g1}};
     if (elem < 0 || elem > 1 || op < 0 || op > 2) return hipErrorInvalidValue;
-    return table[elem][op](law, damped, te, n_tiles, lds, s, m, c, tile0, nl, nc);
+    const int k = (op == kOpVjp && c.gtheta) ? 3 : op;
+    return table[elem][k](law, damped, te, n_tiles, lds, s, m, c, tile0, nl, nc);
 }
 }  // namespace tlfea
 

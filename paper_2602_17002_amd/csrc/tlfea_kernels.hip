@@ -1,6 +1,6 @@
 // One translation unit per (element type, operation): compiled with
 // -DTLFEA_ELEM=<0|1> -DTLFEA_OP=<0|1|2> so the instantiations build in
-// parallel.  The (T10, forward) unit also holds the shared-node kernel.
+// parallel; the adjoint has two units, -DTLFEA_VJP_GT=<0|1>.  The (T10, forward) unit also holds the shared-node kernel.
 #include "tlfea_device.h"
 
 #ifndef TLFEA_ELEM
@@ -10,16 +10,29 @@
 #error "TLFEA_OP must be defined"
 #endif
 
+#ifndef TLFEA_VJP_GT
+#define TLFEA_VJP_GT 0
+#endif
+
 #define TLFEA_CAT2(a, b, c) a##_e##b##_o##c
 #define TLFEA_CAT(a, b, c) TLFEA_CAT2(a, b, c)
+#define TLFEA_CATG2(a, b, c, g) a##_e##b##_o##c##_g##g
+#define TLFEA_CATG(a, b, c, g) TLFEA_CATG2(a, b, c, g)
 
 namespace tlfea {
 
+#if TLFEA_OP == 1
+// the adjoint units: one per gtheta choice (-DTLFEA_VJP_GT=0|1)
+hipError_t TLFEA_CATG(launch_tiles, TLFEA_ELEM, TLFEA_OP, TLFEA_VJP_GT)(int law, int damped, int te, int n_tiles,
+                                                                        size_t lds, hipStream_t s, const DevMesh &m,
+                                                                        const CallArgs &c, int tile0, int nl, int nc)
+#else
 hipError_t TLFEA_CAT(launch_tiles, TLFEA_ELEM, TLFEA_OP)(int law, int damped, int te, int n_tiles, size_t lds,
                                                           hipStream_t s, const DevMesh &m, const CallArgs &c,
                                                           int tile0, int nl, int nc)
+#endif
 {
-    return launch_class<TLFEA_OP, TLFEA_ELEM>(law, damped, te, n_tiles, lds, s, m, c, tile0, nl, nc);
+    return launch_class<TLFEA_OP, TLFEA_ELEM, TLFEA_VJP_GT>(law, damped, te, n_tiles, lds, s, m, c, tile0, nl, nc);
 }
 
 #if TLFEA_OP == 0

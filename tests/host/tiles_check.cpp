@@ -23,7 +23,8 @@ hipError_t launch_zero_count(hipStream_t, unsigned long long *) { return hipErro
 #define TLFEA_STUB(e, o)                                                                                          \
     hipError_t launch_tiles_e##e##_o##o(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, \
                                         int, int, int) { return hipErrorInvalidValue; }
-TLFEA_STUB(0, 0) TLFEA_STUB(0, 1) TLFEA_STUB(0, 2) TLFEA_STUB(1, 0) TLFEA_STUB(1, 1) TLFEA_STUB(1, 2)
+TLFEA_STUB(0, 0) TLFEA_STUB(0, 1_g0) TLFEA_STUB(0, 1_g1) TLFEA_STUB(0, 2)
+TLFEA_STUB(1, 0) TLFEA_STUB(1, 1_g0) TLFEA_STUB(1, 1_g1) TLFEA_STUB(1, 2)
 #undef TLFEA_STUB
 }  // namespace tlfea
 
