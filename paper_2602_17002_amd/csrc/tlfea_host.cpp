@@ -135,14 +135,14 @@ struct tlfea_mesh {
 
 static void free_mesh_memory(tlfea_mesh *m)
 {
-    for (void *p : m->allocations) hipFree(p);
+    for (void *p : m->allocations) (void)hipFree(p);
     m->allocations.clear();
-    for (auto &g : m->graphs) hipGraphExecDestroy(g.exec);
+    for (auto &g : m->graphs) (void)hipGraphExecDestroy(g.exec);
     m->graphs.clear();
     for (int k = 0; k < kNumKernelIds; ++k) {
         for (auto &e : m->pending[k]) {
-            hipEventDestroy(e.first);
-            hipEventDestroy(e.second);
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
         }
         m->pending[k].clear();
     }
@@ -794,7 +794,10 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
     if (st != TLFEA_OK) return st;
     tlfea_mesh *m = new (std::nothrow) tlfea_mesh();
     if (!m) return fail(TLFEA_E_NOMEM, "host allocation failed");
-    hipGetDevice(&m->device);
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return fail(TLFEA_E_DEVICE, "hipGetDevice failed");
+    }
     m->flags = flags;
     m->n_nodes = n_nodes;
     m->n_blocks = n_blocks;
@@ -902,8 +905,8 @@ struct EventPair {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ~EventPair()
     {
-        if (e0) hipEventDestroy(e0);
-        if (e1) hipEventDestroy(e1);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
     }
 };
 
@@ -972,7 +975,7 @@ static tlfea_status run(tlfea_mesh *m, int op, const CallArgs &c, void *stream)
         tlfea_status st = enqueue(m, op, c, s, false);
         hipError_t ec = hipStreamEndCapture(s, &graph);
         if (st != TLFEA_OK) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return st;
         }
         if (ec != hipSuccess) return fail(TLFEA_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
@@ -982,12 +985,12 @@ static tlfea_status run(tlfea_mesh *m, int op, const CallArgs &c, void *stream)
         ge.stream = s;
         ge.stamp = ++m->stamp;
         hipError_t ei = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (ei != hipSuccess) return fail(TLFEA_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
         if (m->graphs.size() >= 8) {
             auto old = std::min_element(m->graphs.begin(), m->graphs.end(),
                                         [](const GraphEntry &a, const GraphEntry &b) { return a.stamp < b.stamp; });
-            hipGraphExecDestroy(old->exec);
+            (void)hipGraphExecDestroy(old->exec);
             m->graphs.erase(old);
         }
         m->graphs.push_back(ge);
@@ -1078,7 +1081,7 @@ static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vecto
         ~Buffers()
         {
             for (double *q : p)
-                if (q) hipFree(q);
+                if (q) (void)hipFree(q);
         }
     } buf;
     for (double *&q : buf.p) HIP_TRY(hipMalloc(&q, nb));
@@ -1162,7 +1165,7 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
 extern "C" void tlfea_destroy_mesh(tlfea_mesh *m)
 {
     if (!m) return;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();   // no enqueued call may still use the mesh
     free_mesh_memory(m);
     delete m;
 }
@@ -1207,8 +1210,8 @@ extern "C" tlfea_status tlfea_get_profile(tlfea_mesh *m, int32_t *counts, double
             HIP_TRY(hipEventElapsedTime(&t, e.first, e.second));
             m->ms[k] += t;
             m->counts[k] += 1;
-            hipEventDestroy(e.first);
-            hipEventDestroy(e.second);
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
         }
         m->pending[k].clear();
         if (counts) counts[k] = m->counts[k];
