@@ -44,7 +44,8 @@ def _run_raw(harness, tmp_path, X, blocks, flags=0):
         for b in blocks:
             fh.write(f"{b.elem} {b.law} {int(b.damped)} {getattr(b, 'tile_elems', 0) or 0} {b.conn.shape[0]}\n")
             fh.write(" ".join(str(int(v)) for v in b.conn.ravel()) + "\n")
-    env = dict(os.environ, LD_LIBRARY_PATH="/opt/rocm/lib:" + os.environ.get("LD_LIBRARY_PATH", ""))
+    env = dict(os.environ, LD_LIBRARY_PATH="/opt/rocm/lib:" + os.environ.get("LD_LIBRARY_PATH", ""),
+               ASAN_OPTIONS="detect_leaks=1")
     return subprocess.run([harness, str(path)], capture_output=True, text=True, env=env, timeout=120)
 
 
@@ -103,3 +104,33 @@ def test_offset_limit_rejects_oversized_mesh(tmp_path_factory, tmp_path):
     big.tile_elems = 64
     r = _run_raw(exe, tmp_path, X2, [big])
     assert "FAIL build_tiles" in r.stdout and "32-bit offset limit" in r.stdout, (r.stdout[-2000:], r.stderr[-2000:])
+
+
+def test_builder_clean_under_address_and_ub_sanitizers(tmp_path_factory, tmp_path):
+    # The mesh builder (tiling, lane order, record positions, tile CSR,
+    # shared-node partials) compiled for the host alone with GCC's address
+    # and undefined-behaviour sanitizers, leak checks on, over T10 tiles of
+    # every size, a multibody mesh in both orders and an H8 block.
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("asan") / "tiles_check_asan")
+    cmd = [gxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-D__HIP_PLATFORM_AMD__", "-w", "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "paper_2602_17002_amd", "csrc"), SRC, "-o", exe, "-L/opt/rocm/lib", "-lamdhip64"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    X, conn = synth.box_t10(8, 6, 4, size=(0.08, 0.06, 0.04))
+    cases = []
+    for te in (64, 128, 192, 256):
+        b = synth.Block(synth.T10, synth.NH, conn, np.array([1.7e6, 0, 1.7e7, 1e4, 0]), damped=True)
+        b.tile_elems = te
+        cases.append((X, [b], 0))
+    p = synth.config_multibody(6, 150, 2000, seed=22)
+    cases += [(p.X, p.blocks, 0), (p.X, p.blocks, 4)]
+    Xh, ch = synth.box_h8(8, 6, 5)
+    cases.append((Xh, [synth.Block(synth.H8, synth.MR, ch, np.array([1.2e6, 0.45e6, 1.7e7, 0, 0]))], 0))
+    for X_, blocks, flags in cases:
+        r = _run_raw(exe, tmp_path, X_, blocks, flags)
+        assert r.returncode == 0 and "runtime error" not in r.stderr, r.stderr[-3000:]
+        assert r.stdout.strip().splitlines()[-1].startswith("OK"), r.stdout[-1000:]
