@@ -104,6 +104,7 @@ struct GraphEntry {
     const void *key[9];
     hipStream_t stream;
     hipGraphExec_t exec;
+    hipEvent_t done;   // recorded after every launch of exec: waited on before exec is destroyed
     uint64_t stamp;
 };
 
@@ -137,7 +138,10 @@ static void free_mesh_memory(tlfea_mesh *m)
 {
     for (void *p : m->allocations) (void)hipFree(p);
     m->allocations.clear();
-    for (auto &g : m->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto &g : m->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipEventDestroy(g.done);
+    }
     m->graphs.clear();
     for (int k = 0; k < kNumKernelIds; ++k) {
         for (auto &e : m->pending[k]) {
@@ -987,18 +991,30 @@ static tlfea_status run(tlfea_mesh *m, int op, const CallArgs &c, void *stream)
         hipError_t ei = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (ei != hipSuccess) return fail(TLFEA_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        ei = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming);
+        if (ei != hipSuccess) {
+            (void)hipGraphExecDestroy(ge.exec);
+            return fail(TLFEA_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(ei));
+        }
         if (m->graphs.size() >= 8) {
+            // the least recently used graph; its last launch may still run
             auto old = std::min_element(m->graphs.begin(), m->graphs.end(),
                                         [](const GraphEntry &a, const GraphEntry &b) { return a.stamp < b.stamp; });
+            const hipError_t ew = hipEventSynchronize(old->done);
             (void)hipGraphExecDestroy(old->exec);
+            (void)hipEventDestroy(old->done);
             m->graphs.erase(old);
+            if (ew != hipSuccess) return fail(TLFEA_E_DEVICE, "waiting for an evicted graph: %s", hipGetErrorString(ew));
         }
         m->graphs.push_back(ge);
         hit = &m->graphs.back();
     }
     hit->stamp = ++m->stamp;
     hipGraphExec_t exec = hit->exec;
-    return timed_launch(m, 4, s, m->prof, "graph", [&] { return hipGraphLaunch(exec, s); });
+    const tlfea_status st = timed_launch(m, 4, s, m->prof, "graph", [&] { return hipGraphLaunch(exec, s); });
+    if (st != TLFEA_OK) return st;
+    HIP_TRY(hipEventRecord(hit->done, s));
+    return TLFEA_OK;
 }
 
 static tlfea_status check_mesh(const tlfea_mesh *m)

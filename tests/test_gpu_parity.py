@@ -368,6 +368,36 @@ def test_multibody_batched_graph_equals_plain_and_oracle():
         assert np.array_equal(fb1, outs[0][0][:, n0:n1])
 
 
+def test_batched_graph_cache_eviction():
+    # A batched mesh keeps one graph per (operation, operand pointers,
+    # stream), at most eight, evicting the least recently used one after its
+    # last launch has finished.  Twelve output buffers, cycled twice on one
+    # stream without synchronising, force evictions while earlier graphs may
+    # still run; every output must equal the plain mesh's bitwise.
+    import torch
+    from paper_2602_17002_amd import BATCHED
+    p = synth.config_multibody(6, 150, 1500, seed=9, directions=True)
+    say("graph cache", len(p.blocks), p.n_elem)
+    plain, batched = mesh_of(p), mesh_of(p, flags=BATCHED)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        x, w = to_dev(p.x), to_dev(p.w)
+        ref_f = to_host(plain.internal_force(x))
+        ref_g = to_host(plain.vjp(x, None, w, want_v=False, want_theta=False)[0])
+        fs = [torch.empty_like(x) for _ in range(12)]
+        gs = [torch.empty_like(x) for _ in range(12)]
+        for rep in range(2):
+            for f, g in zip(fs, gs):
+                f.fill_(float("nan"))
+                g.fill_(float("nan"))
+                batched.internal_force(x, out=f)
+                batched.vjp(x, None, w, want_v=False, want_theta=False, out=(g, None, None))
+        torch.cuda.synchronize()
+    for f, g in zip(fs, gs):
+        assert np.array_equal(to_host(f), ref_f)
+        assert np.array_equal(to_host(g), ref_g)
+
+
 def test_autograd_function():
     import torch
     from paper_2602_17002_amd import TLInternalForce
