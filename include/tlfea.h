@@ -37,6 +37,13 @@
  * - Outputs are overwritten, never accumulated, and must not alias inputs.
  * - A mesh holds device scratch for partial node sums: calls on one mesh must
  *   not overlap in time (issue them on one stream, or synchronise).
+ * - A TLFEA_BATCHED mesh records each call's launches (one per tile class,
+ *   then the shared-node sum) into a hipGraph the first time it sees that
+ *   operation with those operand pointers on that stream, and replays it
+ *   afterwards; it keeps the eight most recently used graphs and waits for an
+ *   evicted graph's last launch before freeing it.  On the null stream, or
+ *   on a stream the caller is capturing, the launches are issued directly
+ *   (the caller's graph then holds them).
  * - Every function returns a tlfea_status; nothing throws.  On a non-OK
  *   status tlfea_last_error() gives a message (thread-local).  Argument
  *   checks happen on the host before any device work is enqueued.
