@@ -164,12 +164,14 @@ tlfea_status tlfea_tangent_jvp(tlfea_mesh *mesh, const double *x, const double *
                                double *df, void *stream);
 
 /*
- * A node numbering under which the nodes of every tile are (nearly)
- * contiguous: order[k] is the caller's node that should become node k
- * (HOST int32[n_nodes], written).  The mesh is unchanged.  Renumbering X,
- * the connectivity and every nodal array once with it, and creating the
- * mesh again from the renumbered data, makes the kernels' node gathers and
- * stores coalesced.  The tiles and their summation order do not depend on
+ * A node numbering suited to the kernels: order[k] is the caller's node that
+ * should become node k (HOST int32[n_nodes], written).  Nodes held by one
+ * tile only come first, tile by tile; the nodes several tiles share follow,
+ * in the order of the first tile that holds them; nodes no element touches
+ * come last.  The mesh is unchanged.  Renumbering X, the connectivity and
+ * every nodal array once with it, and creating the mesh again from the
+ * renumbered data, makes the kernels' node gathers and their stores, and the
+ * shared-node sums' stores, coalesced.  The tiles and their summation order do not depend on
  * node numbers; the node each tile's coordinates are taken relative to may,
  * so results agree with those of the original numbering to rounding.
  */
