@@ -378,6 +378,21 @@ def pmc_summary(trace_dir, fetch_dir, write_dir, commands):
 
 # ---------------------------------------------------------------- main
 
+def trace_summary(name, title, trace_dir, command):
+    """Write profiles/kernel_stats_<name>.md from a rocprofv3 --kernel-trace
+    --stats run: calls, average, min, max and share of every kernel."""
+    os.makedirs(PROFILES, exist_ok=True)
+    stats = _csv_rows(os.path.join(trace_dir, "**", "*kernel_stats.csv"))
+    lines = [f"# Kernel statistics: {title}", "", f"Command: `{command}`", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
+    lines += ["", f"SOURCE_SHA256 {source_hash()}"]
+    with open(os.path.join(PROFILES, f"kernel_stats_{name}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def sq_summary(dirs, commands):
     """Write profiles/sq_counters_c2_fwd_vjp.md from rocprofv3 --pmc runs of
     SQ counters over the bench: the median per dispatch of every counter for
@@ -425,11 +440,18 @@ def main():
                     help="also run one device-to-device copy of this many MiB (a kernel of known "
                          "traffic, used to scale the HBM byte counters of a profiler run)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--trace-summary", nargs=3, metavar=("NAME", "TITLE", "TRACE_DIR"),
+                    help="write profiles/kernel_stats_NAME.md from a rocprofv3 --kernel-trace --stats run")
+    ap.add_argument("--only-c5", action="store_true",
+                    help="time only the 256-body forward + adjoint + tangent graph (for profiling it)")
     ap.add_argument("--sq-summary", nargs="+", metavar="PMC_DIR",
                     help="write profiles/sq_counters_c2_fwd_vjp.md from rocprofv3 --pmc runs of SQ counters")
     ap.add_argument("--commands", default="{}",
                     help="JSON: the profiler command lines (for --pmc-summary / --sq-summary)")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(*args.trace_summary, json.loads(args.commands)["trace"])
+        return
     if args.sq_summary:
         sq_summary(args.sq_summary, json.loads(args.commands))
         return
@@ -440,6 +462,11 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.only_c5:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"batched_c5": batched_c5(max(3, args.steps // 4), 1)}), flush=True)
+        return
 
     import torch
 
