@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose=False):
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
            "-Wall", "-Wextra", "-Wno-unused-parameter", SRC, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -38,10 +38,17 @@ def lib():
         L.oracle_internal_force.argtypes = mesh + [_dp, _dp, _dp]
         L.oracle_energy.argtypes = mesh + [_dp, _dp, _dp, _dp]
         L.oracle_vjp.argtypes = mesh + [_dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_internal_force_par.argtypes = mesh + [_dp, _dp, _dp, C.c_int]
+        L.oracle_vjp_par.argtypes = mesh + [_dp, _dp, _dp, _dp, _dp, _dp, C.c_int]
         L.oracle_jvp.argtypes = mesh + [_dp, _dp, _dp, _dp, _dp]
         L.oracle_element_tangent.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_count_inverted.argtypes = [C.c_int, C.c_int64, _dp, C.c_int64, _ip, _dp,
                                              C.POINTER(C.c_int64), _dp]
+        L.oracle_mass_rule.argtypes = [C.c_int, _dp, _dp]
+        L.oracle_element_mass.argtypes = [C.c_int, C.c_double, _dp, _dp]
+        L.oracle_mass_action.argtypes = [C.c_int, C.c_int64, _dp, C.c_int64, _ip, C.c_double, _dp, _dp]
+        L.oracle_step_residual.argtypes = mesh + [C.c_double, _dp, _dp, _dp, C.c_double, _dp]
+        L.oracle_newton_operator.argtypes = mesh + [C.c_double, _dp, _dp, C.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -126,6 +133,32 @@ def internal_force(X, blocks, x, v=None):
     return f
 
 
+def internal_force_par(X, blocks, x, v=None, threads=1):
+    """internal_force with each block's elements split over ``threads``
+    OpenMP threads (private buffers added in thread order)."""
+    X = _f64(X); x = _f64(x); v = _f64(v)
+    f = np.zeros_like(X)
+    for b in blocks:
+        args, keep = _mesh_args(b, X)
+        _check(lib().oracle_internal_force_par(*args, _d(x), _d(v), _d(f), int(threads)), "internal_force_par")
+    return f
+
+
+def vjp_par(X, blocks, x, v, w, want_gx=True, want_gv=True, want_gtheta=True, threads=1):
+    """vjp with each block's elements split over ``threads`` OpenMP threads."""
+    X = _f64(X); x = _f64(x); v = _f64(v); w = _f64(w)
+    gx = np.zeros_like(X) if want_gx else None
+    gv = np.zeros_like(X) if want_gv else None
+    gts = []
+    for b in blocks:
+        args, keep = _mesh_args(b, X)
+        gt = np.zeros((5, b.conn.shape[0])) if want_gtheta else None
+        _check(lib().oracle_vjp_par(*args, _d(x), _d(v), _d(w), _d(gx), _d(gv), _d(gt), int(threads)), "vjp_par")
+        gts.append(gt)
+    gtheta = np.concatenate(gts, axis=1) if want_gtheta else None
+    return gx, gv, gtheta
+
+
 def energy(X, blocks, x, v=None):
     """(Pi_h, Phi_h): discrete elastic energy and dissipation potential."""
     X = _f64(X); x = _f64(x); v = _f64(v)
@@ -190,3 +223,107 @@ def incident_elements(conn, nodes):
     mask = np.zeros(int(conn.max()) + 1, dtype=bool)
     mask[np.asarray(nodes)] = True
     return np.nonzero(mask[conn].any(axis=1))[0]
+
+
+# ---------------------------------------------------------------- inertia and the step (Sec. 4.1, Sec. 7)
+
+def mass_rule(elem):
+    """(points [nq][3], weights [nq]) of the rule used for the mass integrals."""
+    xi = np.zeros((27, 3)); w = np.zeros(27)
+    nq = lib().oracle_mass_rule(elem, _d(xi), _d(w))
+    return xi[:nq].copy(), w[:nq].copy()
+
+
+def element_mass(elem, rho, Xe):
+    """[nen][nen] element mass m_ij = int rho s_i s_j dV_r; Xe is [3][nen]."""
+    n = nen(elem)
+    M = np.zeros((n, n))
+    _check(lib().oracle_element_mass(elem, float(rho), _d(_f64(Xe)), _d(M)), "element_mass")
+    return M
+
+
+def _rho(b):
+    return float(getattr(b, "rho", 0.0) or 0.0)
+
+
+def mass_action(X, blocks, u):
+    """y = M u (assembled consistent mass, blocks summed in order)."""
+    X = _f64(X); u = _f64(u)
+    y = np.zeros_like(X)
+    for b in blocks:
+        conn = np.ascontiguousarray(b.conn, dtype=np.int32)
+        _check(lib().oracle_mass_action(b.elem, X.shape[1], _d(X), conn.shape[0], conn.ctypes.data_as(_ip),
+                                        _rho(b), _d(u), _d(y)), "mass_action")
+    return y
+
+
+def step_residual(X, blocks, q_n, v_n, v, h, f_ext=None):
+    """g(v) = M (v - v_n)/h + f_int(q_n + h v, v) - f_ext (Sec. 7, no constraints)."""
+    X = _f64(X); q_n = _f64(q_n); v_n = _f64(v_n); v = _f64(v)
+    g = np.zeros_like(X)
+    for b in blocks:
+        args, keep = _mesh_args(b, X)
+        _check(lib().oracle_step_residual(*args, _rho(b), _d(q_n), _d(v_n), _d(v), float(h), _d(g)), "step_residual")
+    if f_ext is not None:
+        g -= _f64(f_ext)
+    return g
+
+
+def newton_operator(X, blocks, q_n, v, h, dv):
+    """(M/h + h K + C) dv at q = q_n + h v: the velocity derivative of g."""
+    X = _f64(X); q_n = _f64(q_n); v = _f64(v); dv = _f64(dv)
+    y = np.zeros_like(X)
+    for b in blocks:
+        args, keep = _mesh_args(b, X)
+        _check(lib().oracle_newton_operator(*args, _rho(b), _d(q_n), _d(v), float(h), _d(dv), _d(y)),
+               "newton_operator")
+    return y
+
+
+def newton_matrix(X, blocks, q_n, v, h):
+    """The assembled (M/h + h K + C) as a scipy CSR matrix over the 3n
+    unknowns ordered [3][n_nodes] (component-major), from the element
+    blocks: the same operator newton_operator applies."""
+    import scipy.sparse as sp
+    X = _f64(X); q_n = _f64(q_n); v = _f64(v)
+    n = X.shape[1]
+    q = np.empty_like(q_n)
+    # the step map with one rounding per entry, as the C oracle forms it
+    q[...] = step_positions(h, v, q_n)
+    rows, cols, vals = [], [], []
+    for b in blocks:
+        th = _theta_e(b)
+        conn = np.ascontiguousarray(b.conn, dtype=np.int32)
+        nn = conn.shape[1]
+        for e in range(conn.shape[0]):
+            c = conn[e]
+            Ke, Ce = element_tangent(b.elem, b.law, th[:, e], X[:, c], q[:, c], v[:, c] if b.damped else None,
+                                     damped=bool(b.damped))
+            Me = element_mass(b.elem, _rho(b), X[:, c])
+            A = h * Ke + Ce + np.kron(Me, np.eye(3)) / h
+            gi = np.array([k * n + c[a] for a in range(nn) for k in range(3)])
+            rows.append(np.repeat(gi, 3 * nn)); cols.append(np.tile(gi, 3 * nn)); vals.append(A.ravel())
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(3 * n, 3 * n))
+
+
+def step_positions(a, x, y):
+    """a * x + y with one rounding per entry (exact product via Dekker's
+    splitting, then a correctly rounded sum of two terms)."""
+    from fractions import Fraction
+    out = np.empty_like(y)
+    xf, yf = x.ravel(), y.ravel()
+    o = out.ravel()
+    fa = Fraction(a)
+    for i in range(xf.size):
+        o[i] = float(fa * Fraction(xf[i]) + Fraction(yf[i]))
+    return out
+
+
+def newton_step(X, blocks, q_n, v_n, v, h, f_ext=None):
+    """One exact Newton step of g(v) = 0: dv = -(M/h + hK + C)^{-1} g(v)
+    (direct sparse solve); returns (v + dv, dv, g)."""
+    import scipy.sparse.linalg as spla
+    g = step_residual(X, blocks, q_n, v_n, v, h, f_ext)
+    A = newton_matrix(X, blocks, q_n, v, h)
+    dv = -spla.spsolve(A.tocsc(), g.ravel()).reshape(g.shape)
+    return v + dv, dv, g

@@ -29,6 +29,9 @@
  *   oracle_energy                                     pinned
  *   oracle_element_tangent, oracle_vjp, oracle_jvp    pinned
  *   oracle_count_inverted                             pinned
+ *   oracle_mass_rule, oracle_element_mass,
+ *   oracle_mass_action                                pinned
+ *   oracle_step_residual, oracle_newton_operator      pinned
  *
  * Layouts: nodal arrays X, x, v, f, w, dx, dv are [3][n_nodes] (row c holds
  * component c of every node); conn is [n_elem][nen] (0-based); theta is
@@ -467,13 +470,15 @@ void oracle_density(int law, int damped, const double *theta, const double *F_, 
 /* Exported: internal force (Sec. 4.3, eq. f_i = int P h_i dV_r)        */
 /* ------------------------------------------------------------------ */
 
-int oracle_internal_force(int elem, int law, int damped, int64_t n_nodes, const double *X,
-                          int64_t n_elem, const int32_t *conn, const double *theta,
-                          const double *x, const double *v, double *f)
+/* Elements [e0, e1) of a block of n_elem elements (conn and theta are the
+ * whole block's arrays), accumulated into f. */
+static int force_range(int elem, int law, int damped, int64_t n_nodes, const double *X,
+                       int64_t n_elem, const int32_t *conn, const double *theta,
+                       const double *x, const double *v, double *f, int64_t e0, int64_t e1)
 {
     elem_t E;
     if (setup(&E, elem)) return OR_E_INVALID;
-    for (int64_t e = 0; e < n_elem; ++e) {
+    for (int64_t e = e0; e < e1; ++e) {
         const int32_t *c = conn + e * E.nen;
         mat_t m = mat_of(law, damped, theta, n_elem, e);
         gather(&E, n_nodes, c, X, x, v);
@@ -489,6 +494,13 @@ int oracle_internal_force(int elem, int law, int damped, int64_t n_nodes, const 
         }
     }
     return OR_OK;
+}
+
+int oracle_internal_force(int elem, int law, int damped, int64_t n_nodes, const double *X,
+                          int64_t n_elem, const int32_t *conn, const double *theta,
+                          const double *x, const double *v, double *f)
+{
+    return force_range(elem, law, damped, n_nodes, X, n_elem, conn, theta, x, v, f, 0, n_elem);
 }
 
 /* Quadrature points whose current deformation gradient has det F <= 0
@@ -732,17 +744,17 @@ int oracle_element_tangent(int elem, int law, int damped, const double *theta,
  * P is linear in each parameter row (SVK: lambda, mu; MR: mu10, mu01, k;
  * Kelvin-Voigt: mu_v, lambda_v).  gtheta rows that a law does not use are
  * written as 0 (row 2 for SVK, row 1 for NH, rows 3-4 when undamped). */
-int oracle_vjp(int elem, int law, int damped, int64_t n_nodes, const double *X,
-               int64_t n_elem, const int32_t *conn, const double *theta,
-               const double *x, const double *v, const double *w,
-               double *gx, double *gv, double *gtheta)
+static int vjp_range(int elem, int law, int damped, int64_t n_nodes, const double *X,
+                     int64_t n_elem, const int32_t *conn, const double *theta,
+                     const double *x, const double *v, const double *w,
+                     double *gx, double *gv, double *gtheta, int64_t e0, int64_t e1)
 {
     elem_t E;
     if (setup(&E, elem)) return OR_E_INVALID;
     const int n3 = 3 * E.nen;
     double *K = malloc(sizeof(double) * n3 * n3), *Cv = malloc(sizeof(double) * n3 * n3);
     int rc = OR_OK;
-    for (int64_t e = 0; e < n_elem && rc == OR_OK; ++e) {
+    for (int64_t e = e0; e < e1 && rc == OR_OK; ++e) {
         const int32_t *c = conn + e * E.nen;
         mat_t m = mat_of(law, damped, theta, n_elem, e);
         gather(&E, n_nodes, c, X, x, v);
@@ -803,6 +815,14 @@ int oracle_vjp(int elem, int law, int damped, int64_t n_nodes, const double *X,
     return rc;
 }
 
+int oracle_vjp(int elem, int law, int damped, int64_t n_nodes, const double *X,
+               int64_t n_elem, const int32_t *conn, const double *theta,
+               const double *x, const double *v, const double *w,
+               double *gx, double *gv, double *gtheta)
+{
+    return vjp_range(elem, law, damped, n_nodes, X, n_elem, conn, theta, x, v, w, gx, gv, gtheta, 0, n_elem);
+}
+
 /* df = sum_e (K^e dx_e + C^e dv_e), accumulated into [3][n_nodes]. */
 int oracle_jvp(int elem, int law, int damped, int64_t n_nodes, const double *X,
                int64_t n_elem, const int32_t *conn, const double *theta,
@@ -834,5 +854,273 @@ int oracle_jvp(int elem, int law, int damped, int64_t n_nodes, const double *X,
     }
     free(K);
     free(Cv);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Multi-threaded runs of the same loops (OpenMP), for timing the      */
+/* oracle on every host core                                           */
+/* ------------------------------------------------------------------ */
+
+/* The block's elements are cut into n_threads contiguous ranges; each thread
+ * accumulates its range into a private nodal buffer with the serial loop
+ * above, and the buffers are then added into the output in thread order,
+ * so the result does not depend on scheduling.  Returns the status of the
+ * first failing range. */
+int oracle_internal_force_par(int elem, int law, int damped, int64_t n_nodes, const double *X,
+                              int64_t n_elem, const int32_t *conn, const double *theta,
+                              const double *x, const double *v, double *f, int n_threads)
+{
+    if (n_threads < 1) n_threads = 1;
+    const size_t nn = 3 * (size_t)n_nodes;
+    double *buf = calloc((size_t)n_threads * nn, sizeof(double));
+    int *rc = calloc((size_t)n_threads, sizeof(int));
+    if (!buf || !rc) { free(buf); free(rc); return OR_E_INVALID; }
+#pragma omp parallel for num_threads(n_threads) schedule(static, 1)
+    for (int t = 0; t < n_threads; ++t) {
+        const int64_t e0 = n_elem * t / n_threads, e1 = n_elem * (t + 1) / n_threads;
+        rc[t] = force_range(elem, law, damped, n_nodes, X, n_elem, conn, theta, x, v, buf + (size_t)t * nn, e0, e1);
+    }
+    int status = OR_OK;
+    for (int t = 0; t < n_threads; ++t) {
+        if (rc[t] && !status) status = rc[t];
+        const double *b = buf + (size_t)t * nn;
+        for (size_t i = 0; i < nn; ++i) f[i] += b[i];
+    }
+    free(buf);
+    free(rc);
+    return status;
+}
+
+int oracle_vjp_par(int elem, int law, int damped, int64_t n_nodes, const double *X,
+                   int64_t n_elem, const int32_t *conn, const double *theta,
+                   const double *x, const double *v, const double *w,
+                   double *gx, double *gv, double *gtheta, int n_threads)
+{
+    if (n_threads < 1) n_threads = 1;
+    const size_t nn = 3 * (size_t)n_nodes;
+    double *bx = gx ? calloc((size_t)n_threads * nn, sizeof(double)) : NULL;
+    double *bv = gv ? calloc((size_t)n_threads * nn, sizeof(double)) : NULL;
+    int *rc = calloc((size_t)n_threads, sizeof(int));
+    if ((gx && !bx) || (gv && !bv) || !rc) { free(bx); free(bv); free(rc); return OR_E_INVALID; }
+#pragma omp parallel for num_threads(n_threads) schedule(static, 1)
+    for (int t = 0; t < n_threads; ++t) {
+        const int64_t e0 = n_elem * t / n_threads, e1 = n_elem * (t + 1) / n_threads;
+        rc[t] = vjp_range(elem, law, damped, n_nodes, X, n_elem, conn, theta, x, v, w,
+                          bx ? bx + (size_t)t * nn : NULL, bv ? bv + (size_t)t * nn : NULL, gtheta, e0, e1);
+    }
+    int status = OR_OK;
+    for (int t = 0; t < n_threads; ++t) {
+        if (rc[t] && !status) status = rc[t];
+        for (size_t i = 0; gx && i < nn; ++i) gx[i] += bx[(size_t)t * nn + i];
+        for (size_t i = 0; gv && i < nn; ++i) gv[i] += bv[(size_t)t * nn + i];
+    }
+    free(bx);
+    free(bv);
+    free(rc);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Inertia: consistent mass (Sec. 4.1) and the backward-Euler step     */
+/* residual of the augmented-Lagrangian formulation without           */
+/* constraints (Sec. 7)                                                */
+/* ------------------------------------------------------------------ */
+
+/* Quadrature of the mass integrals m_ij = int rho s_i s_j dV_r.  The paper
+ * tabulates one rule per element on the parent domain (Sec. 6) and does not
+ * say which rule integrates the mass.  The integrand of a straight-sided
+ * element has twice the degree of the shape functions, so the rule here is
+ * exact for it with positive weights (the element mass matrix is then the
+ * exact Gram matrix of the shape functions, positive definite):
+ *  T10: the 15-point degree-5 rule on the tetrahedron (Hammer, Marlowe and
+ *       Stroud; Stroud's T3:5-1): the centroid, two 4-point orbits
+ *       (a, a, a, 1-3a) with a = (7 -+ sqrt 15)/34, and the 6-point orbit
+ *       (b, b, 1/2-b, 1/2-b) with b = (5 - sqrt 15)/20, in barycentric
+ *       coordinates, weights 16/135, (2665 +- 14 sqrt 15)/37800 and 10/189
+ *       of the volume;
+ *  H8:  2x2x2 Gauss-Legendre (degree 3 per direction). */
+static int mass_rule(int elem, double pts[][3], double *w)
+{
+    if (elem == OR_T10) {
+        const double r15 = sqrt(15.0);
+        const double a[2] = {(7.0 - r15) / 34.0, (7.0 + r15) / 34.0};
+        const double wa[2] = {(2665.0 + 14.0 * r15) / 37800.0, (2665.0 - 14.0 * r15) / 37800.0};
+        const double b = (5.0 - r15) / 20.0, c = 0.5 - b;
+        int q = 0;
+        pts[q][0] = pts[q][1] = pts[q][2] = 0.25;
+        w[q++] = 16.0 / 135.0;
+        for (int o = 0; o < 2; ++o) {
+            /* barycentric (L1, L2, L3, L4) with one of the four equal to 1 - 3a;
+             * parent coordinates are (L2, L3, L4) */
+            for (int k = 0; k < 4; ++k) {
+                double L[4] = {a[o], a[o], a[o], a[o]};
+                L[k] = 1.0 - 3.0 * a[o];
+                pts[q][0] = L[1]; pts[q][1] = L[2]; pts[q][2] = L[3];
+                w[q++] = wa[o];
+            }
+        }
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j) {
+                double L[4] = {c, c, c, c};
+                L[i] = b;
+                L[j] = b;
+                pts[q][0] = L[1]; pts[q][1] = L[2]; pts[q][2] = L[3];
+                w[q++] = 10.0 / 189.0;
+            }
+        for (int k = 0; k < q; ++k) w[k] /= 6.0;   /* volume of the parent tetrahedron */
+        return q;
+    }
+    if (elem == OR_H8) return rule(OR_H8, pts, w);
+    return 0;
+}
+
+#define MAXQM 15
+
+static void shape(int elem, const double *p, double *s)
+{
+    if (elem == OR_T10) t10_shape(p, s); else h8_shape(p, s);
+}
+
+int oracle_mass_rule(int elem, double *xi, double *w)
+{
+    double p[MAXQM][3], ww[MAXQM];
+    const int nq = mass_rule(elem, p, ww);
+    for (int q = 0; q < nq; ++q) {
+        xi[3*q] = p[q][0]; xi[3*q+1] = p[q][1]; xi[3*q+2] = p[q][2];
+        w[q] = ww[q];
+    }
+    return nq;
+}
+
+/* m_ij of one element (Sec. 4.1), [nen][nen]: sum over the mass rule of
+ * w_k rho s_i s_j J_p (Sec. 6 change of variables).  U holds the element's
+ * reference nodes relative to its first node (as in gather()). */
+static int element_mass(int elem, const double U[3][MAXN], double rho, double *Me)
+{
+    const int nen = nen_of(elem);
+    double pts[MAXQM][3], w[MAXQM];
+    const int nq = mass_rule(elem, pts, w);
+    memset(Me, 0, sizeof(double) * nen * nen);
+    for (int q = 0; q < nq; ++q) {
+        double G[MAXN][3], J[3][3], s[MAXN];
+        dshape(elem, pts[q], G);
+        shape(elem, pts[q], s);
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) {
+                double t = 0;
+                for (int a = 0; a < nen; ++a) t += U[i][a] * G[a][k];
+                J[i][k] = t;
+            }
+        const double Jp = det3(J);
+        if (!(Jp > 0)) return OR_E_REF_JACOBIAN;
+        for (int i = 0; i < nen; ++i)
+            for (int j = 0; j < nen; ++j) Me[i * nen + j] += w[q] * rho * s[i] * s[j] * Jp;
+    }
+    return OR_OK;
+}
+
+/* Exported single-element mass matrix; Xe is [3][nen]. */
+int oracle_element_mass(int elem, double rho, const double *Xe, double *Me)
+{
+    const int nen = nen_of(elem);
+    if (!nen) return OR_E_INVALID;
+    double U[3][MAXN];
+    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < nen; ++a) U[i][a] = Xe[i*nen + a] - Xe[i*nen];
+    return element_mass(elem, U, rho, Me);
+}
+
+/* y += M u, M = assembled [m_ij I_3] (Sec. 4.1).  u, y are [3][n_nodes]. */
+int oracle_mass_action(int elem, int64_t n_nodes, const double *X, int64_t n_elem, const int32_t *conn,
+                       double rho, const double *u, double *y)
+{
+    const int nen = nen_of(elem);
+    if (!nen) return OR_E_INVALID;
+    double Me[MAXN * MAXN];
+    for (int64_t e = 0; e < n_elem; ++e) {
+        const int32_t *c = conn + e * nen;
+        double U[3][MAXN];
+        for (int a = 0; a < nen; ++a)
+            for (int i = 0; i < 3; ++i) U[i][a] = X[i*n_nodes + c[a]] - X[i*n_nodes + c[0]];
+        const int rc = element_mass(elem, U, rho, Me);
+        if (rc) return rc;
+        for (int i = 0; i < nen; ++i)
+            for (int r = 0; r < 3; ++r) {
+                double t = 0;
+                for (int j = 0; j < nen; ++j) t += Me[i * nen + j] * u[r*n_nodes + c[j]];
+                y[r*n_nodes + c[i]] += t;
+            }
+    }
+    return OR_OK;
+}
+
+/* The configuration of the step map q(v) = q_n + h v (Sec. 7), formed with
+ * one rounding per entry (a fused multiply-add) so that every evaluation of
+ * the map gives the same positions bit for bit. */
+static double *step_positions(int64_t n_nodes, const double *q_n, const double *v, double h)
+{
+    double *q = malloc(sizeof(double) * 3 * (size_t)n_nodes);
+    if (!q) return NULL;
+    for (int64_t i = 0; i < 3 * n_nodes; ++i) q[i] = fma(h, v[i], q_n[i]);
+    return q;
+}
+
+/* Backward-Euler step residual without constraints (Sec. 7):
+ *   g(v) = M (v - v_n) / h + f_int(q_n + h v, v) - f_ext,
+ * accumulated into g ([3][n_nodes]) for one block; f_ext (may be NULL) is
+ * subtracted by the caller once for the whole mesh (see oracle.py). */
+int oracle_step_residual(int elem, int law, int damped, int64_t n_nodes, const double *X,
+                         int64_t n_elem, const int32_t *conn, const double *theta, double rho,
+                         const double *q_n, const double *v_n, const double *v, double h, double *g)
+{
+    double *q = step_positions(n_nodes, q_n, v, h);
+    double *u = malloc(sizeof(double) * 3 * (size_t)n_nodes);
+    double *Mu = calloc(3 * (size_t)n_nodes, sizeof(double));
+    if (!q || !u || !Mu) { free(q); free(u); free(Mu); return OR_E_INVALID; }
+    for (int64_t i = 0; i < 3 * n_nodes; ++i) u[i] = v[i] - v_n[i];
+    int rc = oracle_mass_action(elem, n_nodes, X, n_elem, conn, rho, u, Mu);
+    if (!rc) {
+        for (int64_t i = 0; i < 3 * n_nodes; ++i) g[i] += Mu[i] / h;
+        rc = force_range(elem, law, damped, n_nodes, X, n_elem, conn, theta, q, damped ? v : NULL, g, 0, n_elem);
+    }
+    free(q); free(u); free(Mu);
+    return rc;
+}
+
+/* The velocity derivative of the residual applied to dv (Sec. 7):
+ *   y = (M / h + h K + C) dv,  K = df_int/dq, C = df_int/dv at (q_n + h v, v),
+ * from the element blocks (App. C and the Kelvin-Voigt blocks), accumulated
+ * into y for one block. */
+int oracle_newton_operator(int elem, int law, int damped, int64_t n_nodes, const double *X,
+                           int64_t n_elem, const int32_t *conn, const double *theta, double rho,
+                           const double *q_n, const double *v, double h, const double *dv, double *y)
+{
+    elem_t E;
+    if (setup(&E, elem)) return OR_E_INVALID;
+    double *q = step_positions(n_nodes, q_n, v, h);
+    const int n3 = 3 * E.nen;
+    double *K = malloc(sizeof(double) * n3 * n3), *Cv = malloc(sizeof(double) * n3 * n3);
+    double Me[MAXN * MAXN];
+    int rc = (q && K && Cv) ? OR_OK : OR_E_INVALID;
+    for (int64_t e = 0; e < n_elem && rc == OR_OK; ++e) {
+        const int32_t *c = conn + e * E.nen;
+        mat_t m = mat_of(law, damped, theta, n_elem, e);
+        gather(&E, n_nodes, c, X, q, damped ? v : NULL);
+        rc = element_blocks(&E, elem, &m, K, Cv);
+        if (!rc) rc = element_mass(elem, E.U, rho, Me);
+        if (rc) break;
+        double de[3 * MAXN];
+        for (int a = 0; a < E.nen; ++a)
+            for (int i = 0; i < 3; ++i) de[3*a + i] = dv[i*n_nodes + c[a]];
+        for (int row = 0; row < n3; ++row) {
+            const int a = row / 3, i = row % 3;
+            double t = 0;
+            for (int col = 0; col < n3; ++col) t += (h * K[row * n3 + col] + Cv[row * n3 + col]) * de[col];
+            for (int b = 0; b < E.nen; ++b) t += Me[a * E.nen + b] / h * de[3*b + i];
+            y[i*n_nodes + c[a]] += t;
+        }
+    }
+    free(q); free(K); free(Cv);
     return rc;
 }

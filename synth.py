@@ -183,6 +183,7 @@ class Block:
     theta: np.ndarray           # [5] default parameters
     damped: bool = False
     theta_e: np.ndarray | None = None   # optional [5][n_elem] per-element parameters
+    rho: float = 0.0                    # reference density (kg/m^3), for inertia
 
     @property
     def n_elem(self):
