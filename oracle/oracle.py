@@ -15,7 +15,7 @@ import numpy as np
 from . import build as _build
 
 _lib = None
-T10, H8 = 0, 1
+T10, H8, Q27 = 0, 1, 2
 SVK, MR, NH = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -71,7 +71,7 @@ def nen(elem):
 
 
 def quadrature(elem):
-    xi = np.zeros((8, 3)); w = np.zeros(8)
+    xi = np.zeros((27, 3)); w = np.zeros(27)
     nq = lib().oracle_quadrature(elem, _d(xi), _d(w))
     return xi[:nq].copy(), w[:nq].copy()
 

@@ -13,6 +13,9 @@
  * quadrature rules and constitutive formulas below are written here from the
  * paper independently of the HIP sources.
  *
+ * Element types: the 10-node tetrahedron and the 27-node hexahedron of
+ * App. A, and the 8-node trilinear hexahedron (not in the paper).
+ *
  * Every element is processed in index order and every quadrature point in
  * table order, following the steps of the paper literally:
  *   U, N, Ndot gathered (Sec. 2.1, eq. r = N s; Sec. 6 isoparametric map),
@@ -47,6 +50,7 @@
 
 #define OR_T10 0
 #define OR_H8 1
+#define OR_Q27 2
 #define OR_SVK 0
 #define OR_MR 1
 #define OR_NH 2
@@ -55,8 +59,8 @@
 #define OR_E_INVALID (-1)
 #define OR_E_REF_JACOBIAN (-3)
 
-#define MAXN 10
-#define MAXQ 8
+#define MAXN 27
+#define MAXQ 27
 
 /* ------------------------------------------------------------------ */
 /* Element library                                                     */
@@ -123,6 +127,48 @@ static void h8_dshape(const double *p, double G[][3])
     }
 }
 
+/* 27-node quadratic hexahedron (App. A, Q27): node n = i + 3 j + 9 k at
+ * parent (i - 1, j - 1, k - 1) (lexicographic, i fastest, the paper's node
+ * table); s_n(xi, eta, zeta) = L_i(xi) L_j(eta) L_k(zeta) with the 1-D
+ * quadratic Lagrange polynomials L_0(s) = s (s - 1) / 2, L_1(s) = 1 - s^2,
+ * L_2(s) = s (s + 1) / 2. */
+static void lagrange2(double s, double L[3], double dL[3])
+{
+    L[0] = 0.5 * s * (s - 1.0);
+    L[1] = 1.0 - s * s;
+    L[2] = 0.5 * s * (s + 1.0);
+    dL[0] = s - 0.5;
+    dL[1] = -2.0 * s;
+    dL[2] = s + 0.5;
+}
+
+static void q27_shape(const double *p, double *s)
+{
+    double Lx[3], Ly[3], Lz[3], d[3];
+    lagrange2(p[0], Lx, d);
+    lagrange2(p[1], Ly, d);
+    lagrange2(p[2], Lz, d);
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) s[i + 3*j + 9*k] = Lx[i] * Ly[j] * Lz[k];
+}
+
+static void q27_dshape(const double *p, double G[][3])
+{
+    double Lx[3], Ly[3], Lz[3], dx[3], dy[3], dz[3];
+    lagrange2(p[0], Lx, dx);
+    lagrange2(p[1], Ly, dy);
+    lagrange2(p[2], Lz, dz);
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
+                const int n = i + 3*j + 9*k;
+                G[n][0] = dx[i] * Ly[j] * Lz[k];
+                G[n][1] = Lx[i] * dy[j] * Lz[k];
+                G[n][2] = Lx[i] * Ly[j] * dz[k];
+            }
+}
+
 /* Quadrature rules tabulated once on the parent element (Sec. 6).  The paper
  * gives no table; the T10 rule is the 5-point degree-3 rule on the unit
  * tetrahedron (centroid weight -4/5, four points at (1/6,1/6,1/6)-type
@@ -138,6 +184,19 @@ static int rule(int elem, double pts[][3], double *w)
             w[q] = (q == 0 ? -4.0/5.0 : 9.0/20.0) / 6.0;
         }
         return 5;
+    }
+    if (elem == OR_Q27) {
+        /* 3x3x3 Gauss-Legendre: points 0, +-sqrt(3/5), weights 8/9, 5/9 */
+        const double g = sqrt(0.6), pt[3] = {-g, 0.0, g}, wt[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+        int q = 0;
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j)
+                for (int i = 0; i < 3; ++i) {
+                    pts[q][0] = pt[i]; pts[q][1] = pt[j]; pts[q][2] = pt[k];
+                    w[q] = wt[i] * wt[j] * wt[k];
+                    ++q;
+                }
+        return 27;
     }
     if (elem == OR_H8) {
         const double g = 1.0 / sqrt(3.0);
@@ -156,11 +215,13 @@ static int rule(int elem, double pts[][3], double *w)
     return 0;
 }
 
-static int nen_of(int elem) { return elem == OR_T10 ? 10 : (elem == OR_H8 ? 8 : 0); }
+static int nen_of(int elem) { return elem == OR_T10 ? 10 : (elem == OR_H8 ? 8 : (elem == OR_Q27 ? 27 : 0)); }
 
 static void dshape(int elem, const double *p, double G[][3])
 {
-    if (elem == OR_T10) t10_dshape(p, G); else h8_dshape(p, G);
+    if (elem == OR_T10) t10_dshape(p, G);
+    else if (elem == OR_H8) h8_dshape(p, G);
+    else q27_dshape(p, G);
 }
 
 /* ------------------------------------------------------------------ */
@@ -433,7 +494,9 @@ int oracle_quadrature(int elem, double *xi, double *w)
 
 void oracle_shape(int elem, const double *xi, double *s)
 {
-    if (elem == OR_T10) t10_shape(xi, s); else h8_shape(xi, s);
+    if (elem == OR_T10) t10_shape(xi, s);
+    else if (elem == OR_H8) h8_shape(xi, s);
+    else q27_shape(xi, s);
 }
 
 void oracle_dshape(int elem, const double *xi, double *G /* [nen][3] */)
@@ -939,7 +1002,8 @@ int oracle_vjp_par(int elem, int law, int damped, int64_t n_nodes, const double 
  *       (b, b, 1/2-b, 1/2-b) with b = (5 - sqrt 15)/20, in barycentric
  *       coordinates, weights 16/135, (2665 +- 14 sqrt 15)/37800 and 10/189
  *       of the volume;
- *  H8:  2x2x2 Gauss-Legendre (degree 3 per direction). */
+ *  H8:  2x2x2 Gauss-Legendre (degree 3 per direction);
+ *  Q27: 3x3x3 Gauss-Legendre (degree 5 per direction). */
 static int mass_rule(int elem, double pts[][3], double *w)
 {
     if (elem == OR_T10) {
@@ -971,15 +1035,19 @@ static int mass_rule(int elem, double pts[][3], double *w)
         for (int k = 0; k < q; ++k) w[k] /= 6.0;   /* volume of the parent tetrahedron */
         return q;
     }
-    if (elem == OR_H8) return rule(OR_H8, pts, w);
+    /* H8 2x2x2 and Q27 3x3x3 Gauss: exact for the mass integrand of a
+     * parallelepiped (degree 2 and 4 per direction) */
+    if (elem == OR_H8 || elem == OR_Q27) return rule(elem, pts, w);
     return 0;
 }
 
-#define MAXQM 15
+#define MAXQM 27
 
 static void shape(int elem, const double *p, double *s)
 {
-    if (elem == OR_T10) t10_shape(p, s); else h8_shape(p, s);
+    if (elem == OR_T10) t10_shape(p, s);
+    else if (elem == OR_H8) h8_shape(p, s);
+    else q27_shape(p, s);
 }
 
 int oracle_mass_rule(int elem, double *xi, double *w)

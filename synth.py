@@ -27,11 +27,11 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-T10, H8 = 0, 1
+T10, H8, Q27 = 0, 1, 2
 SVK, MR, NH = 0, 1, 2
-NEN = {T10: 10, H8: 8}
-NQ = {T10: 5, H8: 8}
-ELEM_NAMES = {T10: "T10", H8: "H8"}
+NEN = {T10: 10, H8: 8, Q27: 27}
+NQ = {T10: 5, H8: 8, Q27: 27}
+ELEM_NAMES = {T10: "T10", H8: "H8", Q27: "Q27"}
 LAW_NAMES = {SVK: "SVK", MR: "MR", NH: "NH"}
 NPAR = 5
 
@@ -119,6 +119,30 @@ def box_h8(nx, ny, nz, size=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
         for dj in (0, 1):
             for di in (0, 1):
                 conn[:, n] = (ci + di) + NX * ((cj + dj) + NY * (ck + dk))
+                n += 1
+    return X, conn.astype(np.int32)
+
+
+def box_q27(nx, ny, nz, size=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
+    """Structured box of nx*ny*nz Q27 cells on the half-cell lattice
+    (2nx+1)(2ny+1)(2nz+1); element node (i, j, k) in {0,1,2}^3 is node
+    i + 3 j + 9 k of the element (lexicographic, i fastest: the paper's Q27
+    node table)."""
+    NX, NY, NZ = 2 * nx + 1, 2 * ny + 1, 2 * nz + 1
+    I, J, K = np.meshgrid(np.arange(NX), np.arange(NY), np.arange(NZ), indexing="ij")
+    I = I.ravel(order="F"); J = J.ravel(order="F"); K = K.ravel(order="F")
+    X = np.empty((3, NX * NY * NZ), dtype=np.float64)
+    X[0] = origin[0] + size[0] / (2 * nx) * I
+    X[1] = origin[1] + size[1] / (2 * ny) * J
+    X[2] = origin[2] + size[2] / (2 * nz) * K
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ci = ci.ravel(order="F"); cj = cj.ravel(order="F"); ck = ck.ravel(order="F")
+    conn = np.empty((ci.size, 27), dtype=np.int64)
+    n = 0
+    for dk in range(3):
+        for dj in range(3):
+            for di in range(3):
+                conn[:, n] = (2 * ci + di) + NX * ((2 * cj + dj) + NY * (2 * ck + dk))
                 n += 1
     return X, conn.astype(np.int32)
 

@@ -48,6 +48,8 @@ def test_mass_rule_h8_is_gauss_2x2x2():
 def _monomials(elem):
     if elem == synth.T10:
         return [(i, j, k) for i in range(3) for j in range(3) for k in range(3) if i + j + k <= 2]
+    if elem == synth.Q27:
+        return [(i, j, k) for i in range(3) for j in range(3) for k in range(3)]
     return [(i, j, k) for i in range(2) for j in range(2) for k in range(2)]
 
 
@@ -81,7 +83,7 @@ def _exact_gram(elem):
     return G
 
 
-@pytest.mark.parametrize("elem", [synth.T10, synth.H8], ids=["T10", "H8"])
+@pytest.mark.parametrize("elem", [synth.T10, synth.H8, synth.Q27], ids=["T10", "H8", "Q27"])
 def test_element_mass_equals_exact_gram_matrix_on_affine_element(elem):
     """For an affine parent-to-reference map u = A xi + b, m_ij = rho det A
     int s_i s_j dxi exactly; the rule is exact for the degree-4 (T10) or
@@ -92,6 +94,8 @@ def test_element_mass_equals_exact_gram_matrix_on_affine_element(elem):
     if elem == synth.T10:
         nodes = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [.5, 0, 0], [.5, .5, 0], [0, .5, 0],
                           [0, 0, .5], [.5, 0, .5], [0, .5, .5]], float)
+    elif elem == synth.Q27:
+        nodes = np.array([[i - 1, j - 1, k - 1] for k in range(3) for j in range(3) for i in range(3)], float)
     else:
         nodes = np.array([[-1, -1, -1], [1, -1, -1], [-1, 1, -1], [1, 1, -1], [-1, -1, 1], [1, -1, 1],
                           [-1, 1, 1], [1, 1, 1]], float)
@@ -107,14 +111,14 @@ def test_element_mass_equals_exact_gram_matrix_on_affine_element(elem):
 def _box(elem, n=(3, 2, 2), cell=0.02, curved=False, seed=2):
     rng = np.random.default_rng(seed)
     size = tuple(k * cell for k in n)
-    X, conn = (synth.box_t10 if elem == synth.T10 else synth.box_h8)(*n, size=size)
+    X, conn = {synth.T10: synth.box_t10, synth.H8: synth.box_h8, synth.Q27: synth.box_q27}[elem](*n, size=size)
     if curved:
         X = synth.curve_midside_t10(X, conn, 0.08, rng) if elem == synth.T10 else X + rng.uniform(
-            -0.05 * cell, 0.05 * cell, X.shape)
+            -0.03 * cell, 0.03 * cell, X.shape)
     return X, conn, size
 
 
-@pytest.mark.parametrize("elem", [synth.T10, synth.H8], ids=["T10", "H8"])
+@pytest.mark.parametrize("elem", [synth.T10, synth.H8, synth.Q27], ids=["T10", "H8", "Q27"])
 def test_mass_of_rigid_translation_is_rho_v(elem):
     """u = c at every node: sum_i (M u)_i = rho V c, the body's mass times c
     (the shape functions sum to one, Sec. 4.1)."""
@@ -131,7 +135,7 @@ def test_mass_of_rigid_translation_is_rho_v(elem):
         assert np.all(y[0] / c[0] > 0)
 
 
-@pytest.mark.parametrize("elem", [synth.T10, synth.H8], ids=["T10", "H8"])
+@pytest.mark.parametrize("elem", [synth.T10, synth.H8, synth.Q27], ids=["T10", "H8", "Q27"])
 def test_assembled_mass_symmetric_positive_definite(elem):
     X, conn, _ = _box(elem, curved=True)
     blk = synth.Block(elem, synth.SVK, conn, np.zeros(5), rho=900.0)

@@ -27,6 +27,8 @@ def blk(elem, law, conn, theta, damped):
 def small_mesh(elem, n=(2, 2, 2), size=(0.2, 0.16, 0.12)):
     if elem == O.T10:
         return synth.box_t10(*n, size=size)
+    if elem == O.Q27:
+        return synth.box_q27(*n, size=size)
     return synth.box_h8(*n, size=size)
 
 
@@ -36,6 +38,9 @@ def single_element(elem, rng, curved=False):
         A = np.eye(3) * 0.1 + rng.uniform(-0.02, 0.02, (3, 3))
         xi = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1],
                        [.5, 0, 0], [.5, .5, 0], [0, .5, 0], [0, 0, .5], [.5, 0, .5], [0, .5, .5]])
+    elif elem == O.Q27:
+        A = np.eye(3) * 0.05 + rng.uniform(-0.01, 0.01, (3, 3))
+        xi = np.array([[i - 1, j - 1, k - 1] for k in range(3) for j in range(3) for i in range(3)], float)
     else:
         A = np.eye(3) * 0.05 + rng.uniform(-0.01, 0.01, (3, 3))
         xi = np.array([[-1, -1, -1], [1, -1, -1], [-1, 1, -1], [1, 1, -1],
@@ -124,7 +129,7 @@ def test_stress_zero_under_rotation(law):
 
 # ---------------------------------------------------------------- mesh level
 
-@pytest.mark.parametrize("elem", [O.T10, O.H8])
+@pytest.mark.parametrize("elem", [O.T10, O.H8, O.Q27])
 @pytest.mark.parametrize("law", list(LAWS))
 def test_reference_state_and_rigid_motion_give_zero_force(elem, law):
     lid, th = LAWS[law]
@@ -143,7 +148,7 @@ def test_reference_state_and_rigid_motion_give_zero_force(elem, law):
     assert np.abs(f).max() < 1e-9 * scale
 
 
-@pytest.mark.parametrize("elem", [O.T10, O.H8])
+@pytest.mark.parametrize("elem", [O.T10, O.H8, O.Q27])
 @pytest.mark.parametrize("law", list(LAWS))
 def test_objectivity_balance_and_angular_momentum(elem, law):
     lid, th = LAWS[law]
@@ -163,7 +168,7 @@ def test_objectivity_balance_and_angular_momentum(elem, law):
     assert np.abs(m).max() < 1e-13 * (np.linalg.norm(x, axis=0) * np.linalg.norm(f, axis=0)).sum()
 
 
-@pytest.mark.parametrize("elem,curved", [(O.T10, False), (O.T10, True), (O.H8, False)])
+@pytest.mark.parametrize("elem,curved", [(O.T10, False), (O.T10, True), (O.H8, False), (O.Q27, False)])
 @pytest.mark.parametrize("law", list(LAWS))
 def test_patch_test_uniform_deformation(elem, law, curved):
     """x = A X, v = B X: F = A and Fdot = B at every point, so interior nodes
@@ -207,7 +212,8 @@ def test_patch_closed_form_stretch(law):
     assert rel(f @ X.T, ref) < 1e-12
 
 
-@pytest.mark.parametrize("elem,curved", [(O.T10, False), (O.T10, True), (O.H8, False), (O.H8, True)])
+@pytest.mark.parametrize("elem,curved", [(O.T10, False), (O.T10, True), (O.H8, False), (O.H8, True),
+                                         (O.Q27, True)])
 @pytest.mark.parametrize("law", list(LAWS))
 def test_force_is_energy_gradient(elem, law, curved):
     """f_i = d/de_i int psi dV (App. C, internal force by definition):
@@ -275,7 +281,7 @@ def test_inverted_reference_element_is_rejected():
 
 # ---------------------------------------------------------------- tangents
 
-@pytest.mark.parametrize("elem,curved", [(O.T10, False), (O.T10, True), (O.H8, True)])
+@pytest.mark.parametrize("elem,curved", [(O.T10, False), (O.T10, True), (O.H8, True), (O.Q27, True)])
 @pytest.mark.parametrize("law", list(LAWS))
 def test_element_tangent_matches_differences(elem, law, curved):
     """Paper's closed-form SVK and Mooney-Rivlin tangents (App. C) plus the
@@ -314,14 +320,14 @@ def test_hyperelastic_tangent_is_symmetric(law):
     assert np.abs(K - K.T).max() < 1e-12 * np.abs(K).max()
 
 
-@pytest.mark.parametrize("elem", [O.T10, O.H8])
+@pytest.mark.parametrize("elem", [O.T10, O.H8, O.Q27])
 @pytest.mark.parametrize("law", list(LAWS))
 def test_assembled_vjp_jvp(elem, law):
     """Adjoint and tangent products on a small mesh: w.(K dx + C dv) equals
     gx.dx + gv.dv, the JVP matches differences of f, and gtheta matches
     exact differences in each parameter row (f is linear in each)."""
     lid, th = LAWS[law]
-    X, conn = small_mesh(elem, n=(2, 2, 1), size=(0.2, 0.2, 0.1))
+    X, conn = small_mesh(elem, n=(2, 2, 1) if elem != O.Q27 else (3, 1, 1), size=(0.2, 0.2, 0.1))
     rng = np.random.default_rng(20)
     ne = conn.shape[0]
     th_e = th[:, None] * rng.uniform(0.5, 2.0, (5, ne))
@@ -376,10 +382,12 @@ def _brute_inverted(elem, X, conn, x):
     return n, mn
 
 
-@pytest.mark.parametrize("elem", [O.T10, O.H8])
+@pytest.mark.parametrize("elem", [O.T10, O.H8, O.Q27])
 def test_inverted_point_count(elem):
     if elem == O.T10:
         X, conn = synth.box_t10(4, 2, 2, size=(0.4, 0.2, 0.2))
+    elif elem == O.Q27:
+        X, conn = synth.box_q27(3, 2, 2, size=(0.3, 0.2, 0.2))
     else:
         X, conn = synth.box_h8(4, 3, 2, size=(0.4, 0.3, 0.2))
     b = blk(elem, O.SVK, conn, LAWS["SVK"][1], False)
@@ -391,7 +399,8 @@ def test_inverted_point_count(elem):
     assert O.count_inverted(X, [b], X * np.array([[1.0], [1.0], [-1.0]]))[0] == n_qp
     assert O.count_inverted(X, [b], np.zeros_like(X))[0] == n_qp
     # tangled: a mixed count, equal to the brute-force sign count
-    x = X + np.random.default_rng(1 if elem == O.T10 else 0).normal(0, 0.04, X.shape)
+    seed, sigma = {O.T10: (1, 0.04), O.H8: (0, 0.04), O.Q27: (3, 0.025)}[elem]
+    x = X + np.random.default_rng(seed).normal(0, sigma, X.shape)
     n, mn = O.count_inverted(X, [b], x)
     nb, mnb = _brute_inverted(elem, X, conn, x)
     assert 0 < n < n_qp
