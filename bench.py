@@ -11,10 +11,17 @@ deformation, velocities N(0, 0.01 m/s), cotangent w ~ N(0, 1).  Inputs are
 resident in HBM before timing.  value = quadrature points per second of the
 whole step.
 
-The line also carries the multibody comparison (skip with --no-batched): 512 bodies of
-200-50,000 elements (mixed T10 / H8, SVK / Neo-Hookean), forward internal
-force of every body, timed as one batched mesh (one hipGraph replay) and as
-one plain mesh per body launched back to back on one stream.
+ms_per_step is the median over the timed steps, each between its own pair of
+HIP events on the stream.
+
+The line also carries: the 204,000-element per-element-parameter body's
+adjoint with parameter gradients and tangent (skip with --no-c4); the
+multibody comparison (skip with --no-batched): 512 bodies of 200-50,000
+elements (mixed T10 / H8, SVK / Neo-Hookean), forward internal force of
+every body, timed as one batched mesh (one hipGraph replay) against one plain
+mesh per body launched back to back on one stream, eagerly and captured into
+one graph; and the 256-body forward + adjoint + tangent graph (skip with
+--no-c5).
 
 Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 
@@ -100,6 +107,17 @@ def flops_per_element(op, elem, law, damped, gtheta=False):
     return tot
 
 
+# consistent-mass action per element: at each point of the mass rule
+# (T10 15 points, H8 8) the interpolation of u (3 x nen FMA), the scaling
+# (3 mul + 1) and the scatter (3 x nen FMA)
+MASS_QP = {T10: 15, H8: 8}
+NEN = {T10: 10, H8: 8}
+
+
+def mass_flops_per_element(elem):
+    return MASS_QP[elem] * (2 * 3 * NEN[elem] + 4 + 2 * 3 * NEN[elem])
+
+
 def bytes_per_call(op, n_nodes, n_elem, nen, damped, theta_rows=0, gtheta=False):
     """Compulsory HBM traffic: every nodal array read once, outputs written
     once, connectivity as int32 read once, optional per-element parameters."""
@@ -153,29 +171,187 @@ def traffic_from_profile(kernel_key):
     return rows.get(kernel_key)
 
 
-def cpu_baseline(prob, budget_s=15.0):
-    """The oracle as it is (serial C, one core) on a bounded sample of the
-    same workload: the first elements of the mesh, forward + adjoint."""
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(prob, budget_s=12.0):
+    """The oracle as it is on a bounded sample of the same workload (the
+    first elements of the mesh, forward + adjoint (gx, gv)): the serial C
+    loop on one core, and the same loop split over every host core the
+    process may use (OpenMP, thread-private node buffers added in thread
+    order)."""
     import copy
 
     import oracle as O
     b = prob.blocks[0]
+    cores = host_cores()
 
-    def run(ne):
+    def run(ne, threads):
         sb = copy.copy(b)
         sb.conn = np.ascontiguousarray(b.conn[:ne])
         t0 = time.perf_counter()
-        O.internal_force(prob.X, [sb], prob.x, prob.v)
-        O.vjp(prob.X, [sb], prob.x, prob.v, prob.w, want_gtheta=False)
+        if threads == 1:
+            O.internal_force(prob.X, [sb], prob.x, prob.v)
+            O.vjp(prob.X, [sb], prob.x, prob.v, prob.w, want_gtheta=False)
+        else:
+            O.internal_force_par(prob.X, [sb], prob.x, prob.v, threads=threads)
+            O.vjp_par(prob.X, [sb], prob.x, prob.v, prob.w, want_gtheta=False, threads=threads)
         return time.perf_counter() - t0
 
-    t_small = run(500)
-    ne = int(min(b.n_elem, max(500, 500 * budget_s / max(t_small, 1e-6))))
-    t = run(ne)
-    nq = ne * 5
-    return {"value": nq / t, "unit": "quad-pts/s", "cores": 1, "kind": "oracle",
-            "sample": f"forward + adjoint (gx, gv) of the first {ne} of {b.n_elem} elements "
-                      f"({nq} quadrature points), serial C oracle, {t:.1f} s"}
+    out = {}
+    for threads in (1, cores):
+        t_small = run(500 * threads, threads)
+        ne = int(min(b.n_elem, max(500, 500 * threads * budget_s / max(t_small, 1e-6))))
+        t = run(ne, threads)
+        nq = ne * 5
+        out[threads] = (nq / t, ne, nq, t)
+    v1, ne1, nq1, t1 = out[1]
+    vn, nen, nqn, tn = out[cores]
+    return {"value": vn, "unit": "quad-pts/s", "cores": cores, "kind": "oracle",
+            "sample": f"forward + adjoint (gx, gv) of the first {nen} of {b.n_elem} elements ({nqn} quadrature "
+                      f"points), C oracle split over {cores} OpenMP threads, {tn:.1f} s",
+            "serial": {"value": v1, "unit": "quad-pts/s", "cores": 1,
+                       "sample": f"first {ne1} elements ({nq1} quadrature points), serial C oracle, {t1:.1f} s"}}
+
+
+def timed(fn, steps, warmup, stream):
+    """Median and mean of `steps` runs of fn, each between its own pair of
+    events on the stream, after `warmup` untimed runs (milliseconds)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return float(np.median(ms)), float(np.mean(ms)), ev[0].elapsed_time(ev[-1])
+
+
+def c4_ops(steps, warmup):
+    """The 204,000-element Neo-Hookean body with per-element parameters:
+    the adjoint with the parameter gradients (gx, gtheta) and the tangent
+    product K dx, each timed alone (median of per-call event pairs)."""
+    import torch
+
+    import synth
+    from paper_2602_17002_amd import Mesh
+    p = synth.config_c4()
+    dev = torch.device("cuda", 0)
+    m = Mesh.from_problem(p)
+    p = p.renumbered(m.node_order())
+    m.close()
+    m = Mesh.from_problem(p)
+    s = torch.cuda.Stream(device=dev)
+    out = {"workload": "C4: 204,000 T10 box 50x40x17 cells, Neo-Hookean, per-element (mu10, k)",
+           "quad_points": p.n_qp}
+    with torch.cuda.stream(s):
+        x, w, dx = (torch.from_numpy(a).to(dev) for a in (p.x, p.w, p.dx))
+        th = torch.from_numpy(p.theta_all()).to(dev)
+        gx, df = torch.empty_like(x), torch.empty_like(x)
+        gt = torch.empty_like(th)
+        ops = (("vjp_gx_gtheta", lambda: m.vjp(x, None, w, th, want_v=False, out=(gx, None, gt)),
+                flops_per_element("vjp", T10, NH, False, gtheta=True)),
+               ("tangent_K_dx", lambda: m.jvp(x, None, dx, None, th, out=df),
+                flops_per_element("jvp", T10, NH, False)))
+        for name, fn, fpe in ops:
+            med, mean, _ = timed(fn, steps, warmup, s)
+            out[name] = {"ms": round(med, 4), "quad_pts_per_s": p.n_qp / (med * 1e-3),
+                         "flops_per_element": fpe,
+                         "frac_fp64_peak": round(fpe * p.n_elem / (med * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+    return out
+
+
+def step_ops(steps, warmup):
+    """The backward-Euler step operations on the 1,020,000-element box with
+    a density (1100 kg/m^3, h = 1e-4 s): the consistent-mass action, the
+    step residual, the Newton operator (each the median of per-call event
+    pairs), and one matrix-free Newton-Krylov step (restarted GMRES to a
+    relative residual of 1e-8), reported with its iteration count."""
+    import torch
+
+    import synth
+    from paper_2602_17002_amd import Mesh
+    p = synth.config_c2()
+    dev = torch.device("cuda", 0)
+    m = Mesh.from_problem(p)
+    p = p.renumbered(m.node_order())
+    m.close()
+    for b in p.blocks:
+        b.rho = 1100.0
+    m = Mesh.from_problem(p)
+    h = 1e-4
+    rng = np.random.default_rng(7)
+    s = torch.cuda.Stream(device=dev)
+    ne, nqp = p.n_elem, p.n_qp
+    out = {"workload": "C2 box with rho = 1100 kg/m^3, h = 1e-4 s: q_n = the C2 state, v_n ~ N(0, 0.3 m/s), "
+                       "v = v_n + N(0, 0.3 m/s)", "quad_points": nqp}
+    with torch.cuda.stream(s):
+        qn = torch.from_numpy(p.x).to(dev)
+        vn = torch.from_numpy(rng.normal(0, 0.3, p.X.shape)).to(dev)
+        v = vn + torch.from_numpy(rng.normal(0, 0.3, p.X.shape)).to(dev)
+        dv = torch.from_numpy(rng.normal(0, 1.0, p.X.shape)).to(dev)
+        y = torch.empty_like(qn)
+        fm = mass_flops_per_element(T10)
+        ops = (("mass_action", lambda: m.mass_action(dv, out=y), fm),
+               ("step_residual", lambda: m.step_residual(qn, vn, v, h, out=y),
+                flops_per_element("fwd", T10, NH, True) + fm),
+               ("newton_operator", lambda: m.newton_operator(qn, v, h, None, dv, out=y),
+                flops_per_element("jvp", T10, NH, True) + fm))
+        for name, fn, fpe in ops:
+            med, mean, _ = timed(fn, steps, warmup, s)
+            out[name] = {"ms": round(med, 4), "quad_pts_per_s": nqp / (med * 1e-3), "flops_per_element": fpe,
+                         "frac_fp64_peak": round(fpe * ne / (med * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+        work = torch.empty(int(m.newton_workspace(30)), dtype=torch.float64, device=dev)
+        vo = torch.empty_like(qn)
+        m.newton_step(qn, vn, v, h, out=vo, work=work, restart=30, max_iters=300, rtol=1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vo, info = m.newton_step(qn, vn, v, h, out=vo, work=work, restart=30, max_iters=300, rtol=1e-8)
+        t1 = time.perf_counter()
+        out["newton_krylov_step"] = {"ms": round((t1 - t0) * 1e3, 3), "gmres_iterations": info["iters"],
+                                     "converged": bool(info["converged"]),
+                                     "relative_residual": info["res_norm"] / max(info["g_norm"], 1e-300),
+                                     "restart": 30, "rtol": 1e-8}
+    return out
+
+
+def joints_ops(steps, warmup, n_joints=1_000_000):
+    """Revolute joints with their five points in random elements of the
+    1,020,000-element box: row-normalised values and the transpose scatter
+    h C^T (lambda + rho c) (median of per-call event pairs)."""
+    import torch
+
+    import synth
+    from paper_2602_17002_amd.joints import Joints
+    p = synth.config_c2()
+    rng = np.random.default_rng(11)
+    conn = p.blocks[0].conn
+    t0 = time.time()
+    els = rng.integers(conn.shape[0], size=(n_joints, 5))
+    bary = rng.dirichlet(np.ones(4), size=(n_joints, 5))
+    dev = torch.device("cuda", 0)
+    J = Joints.from_arrays(p.X, np.full((n_joints, 5), T10, np.int32), conn[els], bary[:, :, 1:])
+    log(f"[bench] {n_joints} joints built in {time.time() - t0:.1f} s")
+    s = torch.cuda.Stream(device=dev)
+    out = {"workload": f"{n_joints} revolute joints, points in random elements of the C2 box"}
+    with torch.cuda.stream(s):
+        q = torch.from_numpy(p.x).to(dev)
+        lam = torch.from_numpy(rng.normal(0, 1, (n_joints, 5))).to(dev)
+        g = torch.empty_like(q)
+        c = torch.empty((n_joints, 5), dtype=torch.float64, device=dev)
+        for name, fn in (("values", lambda: J.values(q)),
+                         ("scatter", lambda: J.scatter(q, lam, 1e4, 1e-3, out=g))):
+            med, mean, _ = timed(fn, steps, warmup, s)
+            out[name] = {"ms": round(med, 4), "joints_per_s": n_joints / (med * 1e-3)}
+    return out
 
 
 def batched_vs_plain(steps, warmup):
@@ -214,24 +390,23 @@ def batched_vs_plain(steps, warmup):
             for (m, _, _), xx, ff in zip(plains, xs, fs):
                 m.internal_force(xx, out=ff)
 
+        # the plain meshes' launches captured into one graph as well, so the
+        # factor is not host dispatch alone
+        run_plain()
+        torch.cuda.synchronize()
+        g_plain = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_plain, stream=s):
+            run_plain()
         res = {}
-        for name, fn in (("batched", run_batched), ("plain", run_plain)):
-            for _ in range(warmup):
-                fn()
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-            for _ in range(steps):
-                fn()
-            e1.record(s)
-            torch.cuda.synchronize()
-            res[name] = e0.elapsed_time(e1) / steps
+        for name, fn in (("batched", run_batched), ("plain", run_plain), ("plain_graph", g_plain.replay)):
+            res[name] = timed(fn, steps, warmup, s)[0]
         same = all(torch.equal(f_b[:, n0:n1], ff) for (_, n0, n1), ff in zip(plains, fs))
     return {"workload": f"C3: {len(p.blocks)} bodies of 200-50,000 elements, mixed T10/H8, SVK/NH, "
                         f"{p.n_elem} elements, forward f_int",
             "ms_batched": round(res["batched"], 4), "ms_plain": round(res["plain"], 4),
+            "ms_plain_graph": round(res["plain_graph"], 4),
             "speedup": round(res["plain"] / res["batched"], 3),
+            "speedup_vs_plain_graph": round(res["plain_graph"] / res["batched"], 3),
             "quad_pts_per_s_batched": p.n_qp / (res["batched"] * 1e-3),
             "bitwise_equal_per_body": bool(same)}
 
@@ -288,19 +463,14 @@ def batched_c5(steps, warmup):
                 m.vjp(xs, None, ws, want_v=False, out=(gg, None, tt))
                 m.jvp(xs, None, ds, out=dd)
 
+        run_plain()
+        torch.cuda.synchronize()
+        g_plain = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_plain, stream=s):
+            run_plain()
         res = {}
-        for name, fn in (("batched", g.replay), ("plain", run_plain)):
-            for _ in range(warmup):
-                fn()
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-            for _ in range(steps):
-                fn()
-            e1.record(s)
-            torch.cuda.synchronize()
-            res[name] = e0.elapsed_time(e1) / steps
+        for name, fn in (("batched", g.replay), ("plain", run_plain), ("plain_graph", g_plain.replay)):
+            res[name] = timed(fn, steps, warmup, s)[0]
         def nrel(a, b):
             return float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
         pairs = [((f[:, n0:n1], ff), (gx[:, n0:n1], gg), (df[:, n0:n1], dd), (gt[:, c0:c1], tt))
@@ -311,8 +481,11 @@ def batched_c5(steps, warmup):
                         f"{p.n_elem} elements, forward + adjoint (gx, gtheta) + tangent in one graph",
             "tile_elems_t10": tuned["tile_elems_t10"], "tile_elems_h8": tuned["tile_elems_h8"],
             "ms_batched": round(res["batched"], 4), "ms_plain": round(res["plain"], 4),
-            "speedup": round(res["plain"] / res["batched"], 3), "bitwise_equal_per_body": same,
-            "max_rel_diff_per_body": diff}
+            "ms_plain_graph": round(res["plain_graph"], 4),
+            "speedup": round(res["plain"] / res["batched"], 3),
+            "speedup_vs_plain_graph": round(res["plain_graph"] / res["batched"], 3),
+            "quad_pts_per_s_batched": p.n_qp / (res["batched"] * 1e-3),
+            "bitwise_equal_per_body": same, "max_rel_diff_per_body": diff}
 
 
 # ---------------------------------------------------------------- profiler summaries
@@ -432,7 +605,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-body batched vs plain comparison")
-    ap.add_argument("--c5", action="store_true", help="also time the 256-body forward + adjoint + tangent graph")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 256-body forward + adjoint + tangent graph")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 204,000-element per-element-parameter adjoint and tangent")
+    ap.add_argument("--no-step", action="store_true", help="skip the mass, step residual, Newton operator and Newton-Krylov step")
+    ap.add_argument("--no-joints", action="store_true", help="skip the revolute-joint values and scatter")
     ap.add_argument("--keep-node-order", action="store_true",
                     help="keep the generator's node numbering instead of the library's suggested order")
     ap.add_argument("--tile", type=int, default=0, help="elements per tile (0 = library default)")
@@ -509,19 +685,11 @@ def main():
             mesh.internal_force(x, v, out=f)
             mesh.vjp(x, v, w, want_theta=False, out=(gx, gv, None))
 
-        for _ in range(args.warmup):
-            step()
-        # whole steps (the value)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_total = e0.elapsed_time(e1)
-        # per-kernel durations (HIP events around every launch, on the launch stream)
+        # whole steps (the value): each step between its own pair of events,
+        # the median over the steps
+        ms_med, ms_mean, ms_total = timed(step, args.steps, args.warmup, stream)
+        # per-kernel durations (HIP events around every launch, on the launch
+        # stream)
         mesh.reset_profile()
         mesh.set_profiling(True)
         for _ in range(args.steps):
@@ -529,8 +697,8 @@ def main():
         torch.cuda.synchronize()
         mesh.set_profiling(False)
         prof = mesh.profile()
-    log(f"[bench] timed {args.steps} steps: {ms_total:.3f} ms; kernels {prof}")
-    ms_step = ms_total / args.steps
+    log(f"[bench] timed {args.steps} steps: {ms_total:.3f} ms, median {ms_med:.4f} ms; kernels {prof}")
+    ms_step = ms_med
     n_qp = prob.n_qp
     value = n_qp / (ms_step * 1e-3)
 
@@ -555,18 +723,33 @@ def main():
     out = {
         "metric": "quad-pts/s f_int fwd+VJP (1M T10 NH), batched vs plain; % HBM/FP64 peak",
         "value": value, "unit": "quad-pts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": ms_step, "ms_per_step_mean": ms_mean, "ms_timed_total": ms_total,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "C2: 1,020,000 T10 box 100x100x17 cells, Neo-Hookean + Kelvin-Voigt, "
                                "forward + adjoint (gx, gv)", "elements": ne, "nodes": nn, "quad_points": n_qp,
-                   "tile_elems": info["tile_elems_t10"]},
+                   "tile_elems": info["tile_elems_t10"],
+                   "step_call": "tlfea_internal_force + tlfea_internal_force_vjp"},
         "kernels_ms_avg": {k: round(t, 4) for k, (c, t) in k_ms.items() if c},
         "roofline": roof,
     }
+    del mesh, x, v, w, f, gx, gv
+    torch.cuda.empty_cache()
+    if not args.no_c4:
+        out["c4"] = c4_ops(args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    if not args.no_step:
+        out["step"] = step_ops(args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    if not args.no_joints:
+        out["joints"] = joints_ops(args.steps, args.warmup)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched_vs_plain"] = batched_vs_plain(max(3, args.steps // 4), 2)
-    if args.c5:
+        torch.cuda.empty_cache()
+    if not args.no_c5:
         out["batched_c5"] = batched_c5(max(3, args.steps // 4), 1)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -34,7 +34,9 @@
  *   current at creation) and a hipStream_t passed as void* (NULL = the null
  *   stream).  Compute calls only enqueue work and return; results are ready
  *   when the stream reaches that point.
- * - Outputs are overwritten, never accumulated, and must not alias inputs.
+ * - Outputs are overwritten, never accumulated.  An output may not overlap
+ *   an input or another output (checked on the host from the array sizes;
+ *   an overlap returns TLFEA_E_INVALID before any device work).
  * - A mesh holds device scratch for partial node sums: calls on one mesh must
  *   not overlap in time (issue them on one stream, or synchronise).
  * - A TLFEA_BATCHED mesh records each call's launches (one per tile class,
@@ -87,8 +89,19 @@ enum {
  * tetrahedron): corners at parent (0,0,0), (1,0,0), (0,1,0), (0,0,1), then
  * mid-edge nodes 1-2, 2-3, 1-3, 1-4, 2-4, 3-4.  H8 (not in the paper) is the
  * trilinear hexahedron on [-1,1]^3 with nodes in the paper's Q27 convention
- * (lexicographic, i fastest).  Quadrature: T10 5-point degree-3 rule, H8
- * 2x2x2 Gauss.
+ * (lexicographic, i fastest).  Quadrature of the internal force: T10 5-point
+ * degree-3 rule, H8 2x2x2 Gauss.
+ *
+ * The quadrature rule is tabulated once on the parent element and reused
+ * for every element (Sec. 6, approximation of integrals): nq points with
+ * weights qp_w[q] and parent gradients dsdxi[q][a][k] = d s_a / d xi_k at
+ * point q (for T10 the rows of the App. A gradient table evaluated at the
+ * points).  Both pointers NULL (and nq 0) select the built-in rule.  A given
+ * table must be the built-in rule to rounding (every entry within 1e-14 of
+ * the largest entry's magnitude, points in the built-in order): the kernels
+ * carry the rule as compile-time constants, so any other rule is refused
+ * with TLFEA_E_UNSUPPORTED.  The tables are read during tlfea_create_mesh
+ * only.
  */
 typedef struct {
     int32_t elem;            /* TLFEA_T10 or TLFEA_H8                          */
@@ -98,6 +111,12 @@ typedef struct {
     double theta[5];         /* default parameter rows (used when theta==NULL) */
     int32_t damped;          /* nonzero: Kelvin-Voigt branch active            */
     int32_t tile_elems;      /* elements per tile: 0 = default, else 64/128/192/256 */
+    int32_t nq;              /* points of qp_w / dsdxi (0 when both are NULL)  */
+    int32_t reserved;        /* must be 0                                      */
+    const double *qp_w;      /* HOST [nq] quadrature weights, or NULL          */
+    const double *dsdxi;     /* HOST [nq][nen][3] parent gradients, or NULL    */
+    double rho;              /* reference density rho_r >= 0 (Sec. 4.1); used by
+                                the mass action and the step residual only     */
 } tlfea_block;
 
 typedef struct {
@@ -112,17 +131,21 @@ typedef struct {
  * Build a mesh on the current HIP device.  X_ref is HOST [3][n_nodes]
  * (reference nodes U, Sec. 6); blocks[b].conn is HOST.  Validation (ids in
  * range, finite coordinates, J_p > 0 at every quadrature point of every
- * element) runs on the host before any device allocation; failures return
- * TLFEA_E_SHAPE / TLFEA_E_REF_JACOBIAN / TLFEA_E_INVALID and leave *out NULL.
- * The mesh reorders elements along a Morton curve (unless TLFEA_KEEP_ORDER)
- * and cuts them into tiles; this never changes the caller-visible order of
- * theta / gtheta.  The tile lists use 32-bit offsets: a mesh that would need
- * more entries (about 200 million T10 elements) returns TLFEA_E_UNSUPPORTED,
- * and such a problem is split over several meshes.  Ownership: the caller
- * keeps its inputs; release the mesh with tlfea_destroy_mesh.
+ * element, Sec. 6) runs on the host before any device allocation; failures
+ * return TLFEA_E_SHAPE / TLFEA_E_REF_JACOBIAN / TLFEA_E_INVALID /
+ * TLFEA_E_UNSUPPORTED and leave *out NULL.  The mesh reorders elements along
+ * a Morton curve (unless TLFEA_KEEP_ORDER) and cuts them into tiles; this
+ * never changes the caller-visible order of theta / gtheta.  The tile lists
+ * use 32-bit offsets: a mesh that would need more entries (about 200
+ * million T10 elements) returns TLFEA_E_UNSUPPORTED, and such a problem is
+ * split over several meshes.  Device uploads (and the autotuner's timing
+ * launches) are issued on `stream` (hipStream_t as void*, NULL = the null
+ * stream), which is synchronised before the call returns.  Ownership: the
+ * caller keeps its inputs; release the mesh with tlfea_destroy_mesh.
  */
 tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X_ref, int32_t n_blocks,
-                               const tlfea_block *blocks, int32_t flags, tlfea_mesh **out);
+                               const tlfea_block *blocks, int32_t flags, void *stream,
+                               tlfea_mesh **out);
 
 /* Free the mesh and its device memory (NULL is a no-op).  Synchronises the
  * device first so no enqueued call still uses it. */
@@ -155,13 +178,142 @@ tlfea_status tlfea_internal_force_vjp(tlfea_mesh *mesh, const double *x, const d
                                       double *gv, double *gtheta, void *stream);
 
 /*
- * Tangent product df = (df/dx) dx + (df/dv) dv (App. C consistent
- * linearisation, K_t = df_int/dq of Sec. 7, plus the Kelvin-Voigt blocks).
- * dx, dv: DEVICE [3][n_nodes] or NULL (treated as zero); df overwritten.
+ * Tangent product df = (df/dx) dx + (df/dv) dv + (df/dtheta) dtheta (App. C
+ * consistent linearisation, K_t = df_int/dq of Sec. 7, plus the
+ * Kelvin-Voigt blocks).  The stress is linear in every parameter row
+ * (Sec. 3.2: SVK in (lambda, mu), Mooney-Rivlin in (mu10, mu01, k),
+ * Kelvin-Voigt in (mu_v, lambda_v)), so the parameter term is the internal
+ * force evaluated with theta = dtheta; the kernels add it per quadrature
+ * point.  dx, dv: DEVICE [3][n_nodes], dtheta: DEVICE [5][n_elem]; each may
+ * be NULL (treated as zero); df overwritten.
  */
 tlfea_status tlfea_tangent_jvp(tlfea_mesh *mesh, const double *x, const double *v,
                                const double *theta, const double *dx, const double *dv,
-                               double *df, void *stream);
+                               const double *dtheta, double *df, void *stream);
+
+/*
+ * Consistent-mass action y = M u (Sec. 4.1): m_ij = int rho_r s_i s_j dV_r,
+ * M = [m_ij I_3] assembled over every block with its density rho (blocks
+ * with rho = 0 contribute nothing).  The mass integrals use a rule exact for
+ * straight-sided elements (the paper tabulates one rule per element on the
+ * parent domain, Sec. 6, and does not name the mass rule): T10 the 15-point
+ * degree-5 rule, H8 2x2x2 Gauss; rho w_q J_p(xi_q) is formed once at mesh
+ * creation.  u, y: DEVICE [3][n_nodes]; y overwritten.
+ */
+tlfea_status tlfea_mass_action(tlfea_mesh *mesh, const double *u, double *y, void *stream);
+
+/*
+ * Residual of the backward-Euler step of the augmented-Lagrangian
+ * formulation without constraints (Sec. 7):
+ *   g(v) = M (v - v_n) / h + f_int(q(v), v) - f_ext,   q(v) = q_n + h v,
+ * with M the consistent mass (Sec. 4.1, as tlfea_mass_action) and f_int the
+ * internal force (Sec. 4.3) at the step configuration.  q(v) is formed per
+ * entry with one rounding (fused multiply-add).  q_n, v_n, v, f_ext, g:
+ * DEVICE [3][n_nodes]; f_ext may be NULL (zero); theta as for
+ * tlfea_internal_force; h > 0 (TLFEA_E_INVALID otherwise); g overwritten.
+ * The constraint term h C_q^T (lambda + rho c) of the full residual is not
+ * part of this call.
+ */
+tlfea_status tlfea_step_residual(tlfea_mesh *mesh, const double *q_n, const double *v_n,
+                                 const double *v, double h, const double *theta,
+                                 const double *f_ext, double *g, void *stream);
+
+/*
+ * The derivative of tlfea_step_residual in v applied to dv (Sec. 7, the
+ * matrix-free Newton operator):
+ *   y = (M / h + h K + C) dv,   K = df_int/dq, C = df_int/dv at (q(v), v),
+ * K and C as in tlfea_tangent_jvp (App. C plus the Kelvin-Voigt blocks).
+ * q_n, v, dv, y: DEVICE [3][n_nodes]; y overwritten; h > 0.
+ */
+tlfea_status tlfea_newton_operator(tlfea_mesh *mesh, const double *q_n, const double *v, double h,
+                                   const double *theta, const double *dv, double *y, void *stream);
+
+/* Krylov options and report of tlfea_newton_step. */
+typedef struct {
+    int32_t restart;     /* Krylov basis size m of restarted GMRES, 1..200   */
+    int32_t max_iters;   /* total inner iterations, >= 1                      */
+    double rtol;         /* stop when ||A dv + g|| <= rtol ||g||, >= 0        */
+} tlfea_krylov_opts;
+
+typedef struct {
+    int32_t iters;       /* inner iterations (operator products) taken        */
+    int32_t converged;   /* 1 when the final ||A dv + g|| <= rtol ||g||       */
+    double g_norm;       /* ||g(v)||_2 (the step residual at the input v)     */
+    double res_norm;     /* ||A dv + g||_2, recomputed from the final dv      */
+} tlfea_krylov_info;
+
+/* Doubles of device workspace tlfea_newton_step needs for a basis of
+ * `restart` vectors: (restart + 5) * 3 n_nodes + 2048. */
+tlfea_status tlfea_newton_workspace(const tlfea_mesh *mesh, int32_t restart, int64_t *n_doubles);
+
+/*
+ * One matrix-free Newton-Krylov step on the step residual g(v) of Sec. 7
+ * (tlfea_step_residual): dv solves (M/h + h K + C) dv = -g(v) by restarted
+ * GMRES (Saad and Schultz) from dv = 0, every operator product one
+ * tlfea_newton_operator pass, classical Gram-Schmidt applied twice, the
+ * small least-squares problem by Givens rotations on the host; the dot
+ * products are summed in a fixed order, so the result is bitwise
+ * repeatable.  v_out = v + dv (DEVICE [3][n_nodes], overwritten).  work:
+ * DEVICE workspace of at least tlfea_newton_workspace doubles, owned by the
+ * caller, contents undefined on return.  info (HOST) reports the
+ * iterations, convergence and residual norms.  The call synchronises the
+ * stream (the solver's scalars live on the host); not converging within
+ * max_iters is not an error (info->converged = 0).
+ */
+tlfea_status tlfea_newton_step(tlfea_mesh *mesh, const double *q_n, const double *v_n, const double *v,
+                               double h, const double *theta, const double *f_ext,
+                               const tlfea_krylov_opts *opts, double *v_out, double *work,
+                               int64_t work_len, tlfea_krylov_info *info, void *stream);
+
+/*
+ * Joint constraints (Sec. 2.2).  A material point is given by its hosting
+ * element (type and node ids in the element's node order) and its parent
+ * coordinates; its current position is the point evaluation r = N(t) s(xi)
+ * (Sec. 2.1).  A revolute joint has points P, Q on body b and R, S, T on
+ * body c, directions a = r_Q - r_P, b_1 = r_S - r_R, b_2 = r_T - r_R, and the
+ * five rows
+ *   c = [e_x.(r_R - r_P), e_y.(r_R - r_P), e_z.(r_R - r_P), a.b_1 - f_1, a.b_2 - f_2]
+ * (three coordinate-difference rows, two dot-product-1 rows), f_j = a_0.b_j0
+ * from the reference configuration.  Rows are normalised by the constant
+ * weights of App. B.1: 1 for the CD rows, 1/sqrt(|a_0|^2 + |b_j0|^2) for the
+ * DP1 rows: c_hat = W c, C_hat = W dc/dq.
+ */
+typedef struct tlfea_joints tlfea_joints;   /* opaque, immutable */
+
+typedef struct {
+    int32_t elem;           /* TLFEA_T10 or TLFEA_H8: the hosting element's type  */
+    int32_t nodes[27];      /* its node ids, element node order (first nen used)  */
+    double xi[3];           /* parent coordinates of the material point           */
+} tlfea_point;
+
+typedef struct {
+    tlfea_point P, Q, R, S, T;
+} tlfea_revolute;
+
+/* Build a joint set on the current device from HOST inputs: X_ref
+ * [3][n_nodes] (for f_j and the row weights) and the joints.  Uploads are
+ * issued on `stream`, synchronised before return.  TLFEA_E_SHAPE for a node
+ * out of range, TLFEA_E_INVALID for an unknown element type, a non-finite
+ * coordinate or reference directions that vanish. */
+tlfea_status tlfea_create_joints(int64_t n_nodes, const double *X_ref, int32_t n_joints,
+                                 const tlfea_revolute *joints, void *stream, tlfea_joints **out);
+void tlfea_destroy_joints(tlfea_joints *joints);
+
+/* Row-normalised constraint values c_hat at positions q (DEVICE [3][n_nodes]);
+ * c: DEVICE [n_joints][5], overwritten. */
+tlfea_status tlfea_joint_values(tlfea_joints *joints, const double *q, double *c, void *stream);
+
+/*
+ * The constraint term of the step residual (Sec. 2.2 residual insertion,
+ * Sec. 7): g (+)= h C_hat(q)^T (lambda + rho c_hat(q)), assembled per node
+ * in a fixed order (no atomics; bitwise repeatable) without forming C_hat.
+ * q, g: DEVICE [3][n_nodes]; lambda: DEVICE [n_joints][5] or NULL (zero);
+ * accumulate = 0 overwrites g (nodes of no joint get 0), nonzero adds to
+ * it.  The joint set holds device scratch: calls on one joint set must not
+ * overlap in time.
+ */
+tlfea_status tlfea_joint_scatter(tlfea_joints *joints, const double *q, const double *lambda, double rho,
+                                 double h, double *g, int32_t accumulate, void *stream);
 
 /*
  * A node numbering suited to the kernels: order[k] is the caller's node that
@@ -198,11 +350,12 @@ const char *tlfea_last_error(void);
  * synchronises those events and returns, per kernel id, the number of
  * launches and their summed duration in milliseconds; reset clears them.
  * Kernel ids: 0 forward tile, 1 adjoint tile, 2 tangent tile, 3 halo
- * reduction, 4 whole batched graph replay.  counts: HOST
+ * reduction, 4 whole batched graph replay, 5 step-residual tile, 6 Newton
+ * operator tile, 7 mass-action tile.  counts: HOST
  * int32[TLFEA_NUM_KERNEL_IDS], ms: HOST double[TLFEA_NUM_KERNEL_IDS]; either
  * may be NULL.
  */
-#define TLFEA_NUM_KERNEL_IDS 5
+#define TLFEA_NUM_KERNEL_IDS 8
 tlfea_status tlfea_set_profiling(tlfea_mesh *mesh, int32_t enable);
 tlfea_status tlfea_get_profile(tlfea_mesh *mesh, int32_t *counts, double *ms);
 tlfea_status tlfea_reset_profile(tlfea_mesh *mesh);

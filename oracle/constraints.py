@@ -91,3 +91,17 @@ def revolute_scatter(X, q, joints, lam=None, rho=0.0, h=1.0):
     eta = (np.zeros_like(c) if lam is None else np.asarray(lam, dtype=np.float64).ravel()) + rho * c
     J = revolute_jacobian(X, q, joints)
     return (h * (J.T @ eta)).reshape(3, q.shape[1])
+
+
+def revolute_scatter_local(X, q, joints, lam=None, rho=0.0, h=1.0):
+    """revolute_scatter evaluated joint by joint on the joint's own nodes
+    (the same formulas; the dense Jacobian of a large mesh would not fit)."""
+    out = np.zeros_like(q, dtype=np.float64)
+    lam = None if lam is None else np.asarray(lam, dtype=np.float64).reshape(len(joints), 5)
+    for j, jt in enumerate(joints):
+        nodes = sorted({int(n) for k in POINTS for n in jt[k][1]})
+        loc = {n: i for i, n in enumerate(nodes)}
+        jl = {k: (jt[k][0], [loc[int(n)] for n in jt[k][1]], jt[k][2]) for k in POINTS}
+        g = revolute_scatter(X[:, nodes], q[:, nodes], [jl], None if lam is None else lam[j:j + 1], rho, h)
+        out[:, nodes] += g
+    return out

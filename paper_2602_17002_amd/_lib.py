@@ -17,17 +17,23 @@ STATUS_NAMES = {0: "TLFEA_OK", -1: "TLFEA_E_INVALID", -2: "TLFEA_E_SHAPE", -3: "
 T10, H8 = 0, 1
 SVK, MR, NH = 0, 1, 2
 PLAIN, BATCHED, AUTOTUNE, KEEP_ORDER = 0, 1, 2, 4
-KERNEL_IDS = ("forward_tile", "adjoint_tile", "tangent_tile", "halo", "batched_graph")
+KERNEL_IDS = ("forward_tile", "adjoint_tile", "tangent_tile", "halo", "batched_graph", "residual_tile",
+              "newton_tile", "mass_tile")
 
 EXPORTS = ("tlfea_create_mesh", "tlfea_destroy_mesh", "tlfea_get_mesh_info", "tlfea_internal_force",
            "tlfea_internal_force_vjp", "tlfea_tangent_jvp", "tlfea_last_error", "tlfea_set_profiling",
-           "tlfea_get_profile", "tlfea_reset_profile", "tlfea_node_order", "tlfea_count_inverted")
+           "tlfea_get_profile", "tlfea_reset_profile", "tlfea_node_order", "tlfea_count_inverted", "tlfea_mass_action", "tlfea_step_residual", "tlfea_newton_operator",
+           "tlfea_newton_workspace", "tlfea_newton_step", "tlfea_create_joints", "tlfea_destroy_joints",
+           "tlfea_joint_values", "tlfea_joint_scatter")
 
 
 class Block(C.Structure):
     _fields_ = [("elem", C.c_int32), ("law", C.c_int32), ("n_elem", C.c_int64),
                 ("conn", C.POINTER(C.c_int32)), ("theta", C.c_double * 5),
-                ("damped", C.c_int32), ("tile_elems", C.c_int32)]
+                ("damped", C.c_int32), ("tile_elems", C.c_int32),
+                ("nq", C.c_int32), ("reserved", C.c_int32),
+                ("qp_w", C.POINTER(C.c_double)), ("dsdxi", C.POINTER(C.c_double)),
+                ("rho", C.c_double)]
 
 
 class MeshInfo(C.Structure):
@@ -36,6 +42,22 @@ class MeshInfo(C.Structure):
                 ("n_blocks", C.c_int32), ("flags", C.c_int32),
                 ("tile_elems_t10", C.c_int32), ("tile_elems_h8", C.c_int32),
                 ("device_bytes", C.c_int64)]
+
+
+class KrylovOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rtol", C.c_double)]
+
+
+class KrylovInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("g_norm", C.c_double), ("res_norm", C.c_double)]
+
+
+class Point(C.Structure):
+    _fields_ = [("elem", C.c_int32), ("nodes", C.c_int32 * 27), ("xi", C.c_double * 3)]
+
+
+class Revolute(C.Structure):
+    _fields_ = [("P", Point), ("Q", Point), ("R", Point), ("S", Point), ("T", Point)]
 
 
 class TlfeaError(RuntimeError):
@@ -57,7 +79,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, dp = C.c_void_p, C.c_void_p
     L.tlfea_create_mesh.argtypes = [C.c_int64, C.POINTER(C.c_double), C.c_int32, C.POINTER(Block), C.c_int32,
-                                    C.POINTER(vp)]
+                                    vp, C.POINTER(vp)]
     L.tlfea_create_mesh.restype = C.c_int
     L.tlfea_destroy_mesh.argtypes = [vp]
     L.tlfea_destroy_mesh.restype = None
@@ -67,9 +89,29 @@ def lib():
     L.tlfea_internal_force.restype = C.c_int
     L.tlfea_internal_force_vjp.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
     L.tlfea_internal_force_vjp.restype = C.c_int
-    L.tlfea_tangent_jvp.argtypes = [vp, dp, dp, dp, dp, dp, dp, vp]
+    L.tlfea_tangent_jvp.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
     L.tlfea_tangent_jvp.restype = C.c_int
     L.tlfea_count_inverted.argtypes = [vp, dp, vp, vp]
+    L.tlfea_mass_action.argtypes = [vp, dp, dp, vp]
+    L.tlfea_mass_action.restype = C.c_int
+    L.tlfea_step_residual.argtypes = [vp, dp, dp, dp, C.c_double, dp, dp, dp, vp]
+    L.tlfea_step_residual.restype = C.c_int
+    L.tlfea_newton_operator.argtypes = [vp, dp, dp, C.c_double, dp, dp, dp, vp]
+    L.tlfea_newton_operator.restype = C.c_int
+    L.tlfea_newton_workspace.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
+    L.tlfea_newton_workspace.restype = C.c_int
+    L.tlfea_newton_step.argtypes = [vp, dp, dp, dp, C.c_double, dp, dp, C.POINTER(KrylovOpts), dp, dp, C.c_int64,
+                                    C.POINTER(KrylovInfo), vp]
+    L.tlfea_newton_step.restype = C.c_int
+    L.tlfea_create_joints.argtypes = [C.c_int64, C.POINTER(C.c_double), C.c_int32, C.POINTER(Revolute), vp,
+                                      C.POINTER(vp)]
+    L.tlfea_create_joints.restype = C.c_int
+    L.tlfea_destroy_joints.argtypes = [vp]
+    L.tlfea_destroy_joints.restype = None
+    L.tlfea_joint_values.argtypes = [vp, dp, dp, vp]
+    L.tlfea_joint_values.restype = C.c_int
+    L.tlfea_joint_scatter.argtypes = [vp, dp, dp, C.c_double, C.c_double, dp, C.c_int32, vp]
+    L.tlfea_joint_scatter.restype = C.c_int
     L.tlfea_count_inverted.restype = C.c_int
     L.tlfea_last_error.argtypes = []
     L.tlfea_last_error.restype = C.c_char_p

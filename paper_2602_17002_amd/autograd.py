@@ -2,10 +2,8 @@
 
 Reverse mode: backward(w) = (gx, gv, gtheta) from tlfea_internal_force_vjp,
 with F recomputed from x inside the adjoint kernel (nothing but the inputs is
-saved).  Forward mode: jvp(dx, dv, dtheta) = K dx + C dv + f(x, v; dtheta),
-the last term because the stress is linear in the whole parameter vector
-(SVK in (lambda, mu), Mooney-Rivlin in (mu10, mu01, k), Kelvin-Voigt in
-(mu_v, lambda_v); Sec. 3.2).
+saved).  Forward mode: jvp(dx, dv, dtheta) = K dx + C dv + (df/dtheta) dtheta
+from tlfea_tangent_jvp, which forms all three terms in its kernels.
 """
 from __future__ import annotations
 
@@ -35,10 +33,7 @@ class TLInternalForce(torch.autograd.Function):
     @staticmethod
     def jvp(ctx, dx, dv, dtheta, _dmesh):
         x, v, theta = ctx.saved_tensors
-        df = ctx.mesh.jvp(x, v, dx, dv, theta)
-        if dtheta is not None:
-            df = df + ctx.mesh.internal_force(x, v, dtheta)
-        return df
+        return ctx.mesh.jvp(x, v, dx, dv, theta, dtheta=dtheta)
 
 
 def internal_force(x, v, theta, mesh):

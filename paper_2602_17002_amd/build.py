@@ -10,17 +10,22 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtlfea.so")
 KERNELS = os.path.join(CSRC, "tlfea_kernels.hip")
+VECTOR = os.path.join(CSRC, "tlfea_vec.hip")
+JOINTS = os.path.join(CSRC, "tlfea_joints.hip")
 HOST = os.path.join(CSRC, "tlfea_host.cpp")
-# (element type, operation, adjoint with parameter gradients) units of
-# tlfea_kernels.hip; the adjoint is compiled once without and once with them
-UNITS = [(e, o, g) for e in (0, 1) for o in (0, 1, 2) for g in ((0, 1) if o == 1 else (0,))]
+# (element type, operation, adjoint with parameter gradients, variant) units
+# of tlfea_kernels.hip; the adjoint is compiled once without and once with
+# the parameter gradients, the forward and the tangent once plain and once
+# as their step variant (step residual, Newton operator)
+UNITS = [(e, o, g, md) for e in (0, 1) for o in (0, 1, 2) for g in ((0, 1) if o == 1 else (0,))
+         for md in ((0, 1) if o != 1 else (0,))]
 # extra compiler flags per unit (element, operation, gradients): the adjoint
 # holds two sets of nodal accumulators, and the scheduler that minimises
 # register pressure keeps it (nearly) free of spills at two waves per SIMD.
 # The T10 adjoint with the parameter gradients spills either way, and LLVM's
 # default schedule runs it 7-13 % faster; the H8 one keeps the other.
 _MAXOCC = ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"]
-UNIT_FLAGS = {(0, 1, 0): _MAXOCC, (1, 1, 0): _MAXOCC, (1, 1, 1): _MAXOCC}
+UNIT_FLAGS = {(0, 1, 0, 0): _MAXOCC, (1, 1, 0, 0): _MAXOCC, (1, 1, 1, 0): _MAXOCC}
 
 
 def hipcc():
@@ -41,11 +46,13 @@ def build(verbose=False, resource_usage=False):
               "-I", INCLUDE, "-I", CSRC]
     if resource_usage:
         common += ["-Rpass-analysis=kernel-resource-usage"]
-    jobs_list = [(HOST, [], os.path.join(CSRC, "tlfea_host.o"))]
-    for e, o, g in UNITS:
-        jobs_list.append((KERNELS, ["-x", "hip", f"-DTLFEA_ELEM={e}", f"-DTLFEA_OP={o}", f"-DTLFEA_VJP_GT={g}"]
-                          + UNIT_FLAGS.get((e, o, g), []),
-                          os.path.join(CSRC, f"tlfea_kernels_e{e}_o{o}_g{g}.o")))
+    jobs_list = [(HOST, [], os.path.join(CSRC, "tlfea_host.o")),
+                 (VECTOR, ["-x", "hip"], os.path.join(CSRC, "tlfea_vec.o")),
+                 (JOINTS, ["-x", "hip"], os.path.join(CSRC, "tlfea_joints.o"))]
+    for e, o, g, md in UNITS:
+        jobs_list.append((KERNELS, ["-x", "hip", f"-DTLFEA_ELEM={e}", f"-DTLFEA_OP={o}", f"-DTLFEA_VJP_GT={g}",
+                                    f"-DTLFEA_MODE={md}"] + UNIT_FLAGS.get((e, o, g, md), []),
+                          os.path.join(CSRC, f"tlfea_kernels_e{e}_o{o}_g{g}_m{md}.o")))
     for src, extra, obj in jobs_list:
         cmd = common + extra + ["-c", src, "-o", obj]
         if verbose:

@@ -124,8 +124,14 @@ __device__ __forceinline__ void qp_fence() { __asm__ __volatile__("" ::: "memory
 
 // G = sum_a s_a (ds_a/dxi at point Q)^T for the field at s (a pointer into
 // the first record at that field's offset); zero gradient entries are
-// removed at compile time.
-template <int ELEM, int Q, int NEN>
+// removed at compile time.  For positions (REL) the sum is taken over the
+// differences s_a - s_0 to the element's first node, which is the same sum
+// because the parent gradients of an element sum to zero, and whose products
+// only cancel over one element instead of over the tile.  Each difference is
+// the nodes' coordinate difference rounded once: the current positions of
+// these kernels are staged raw, and the reference ones relative to the tile's
+// reference node only where that subtraction was exact.
+template <int ELEM, int Q, int NEN, bool REL = false>
 __device__ __forceinline__ void grad_field(const double *__restrict__ s, const int (&na)[NEN], m3 &G)
 {
     using E = ElemDef<ELEM>;
@@ -134,18 +140,26 @@ __device__ __forceinline__ void grad_field(const double *__restrict__ s, const i
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) G[i][k] = 0.0;
+    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+    if constexpr (REL) {
+        o0 = s[na[0]];
+        o1 = s[na[0] + 1];
+        o2 = s[na[0] + 2];
+    }
     static_for<NEN>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        const double x0 = s[na[a]], x1 = s[na[a] + 1], x2 = s[na[a] + 2];
-        static_for<3>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            constexpr double g = E::grad(Q, a, k);
-            if constexpr (g != 0.0) {
-                G[0][k] += x0 * g;
-                G[1][k] += x1 * g;
-                G[2][k] += x2 * g;
-            }
-        });
+        if constexpr (!REL || a > 0) {
+            const double x0 = s[na[a]] - o0, x1 = s[na[a] + 1] - o1, x2 = s[na[a] + 2] - o2;
+            static_for<3>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr double g = E::grad(Q, a, k);
+                if constexpr (g != 0.0) {
+                    G[0][k] += x0 * g;
+                    G[1][k] += x1 * g;
+                    G[2][k] += x2 * g;
+                }
+            });
+        }
     });
 }
 
@@ -187,15 +201,15 @@ __device__ __forceinline__ void finish_last_node(double (&out)[NEN][3])
 }
 
 // Reference geometry at point Q (Sec. 6): J = U dS/dxi, J_p = det J,
-// K = cof(J) = J_p J^{-T} and r = 1 / J_p.  Evaluated at every point from
+// K = cof(J) = J_p J^{-T} and r = 1 / J_p; REL as for grad_field.  Evaluated at every point from
 // all nodes: straight-sided elements have a constant J only up to the
 // rounding of their mid-edge coordinates, which the bulk response amplifies.
-template <int ELEM, int Q, int NEN>
+template <int ELEM, int Q, int NEN, bool REL = false>
 __device__ __forceinline__ void ref_geometry(const double *__restrict__ sX, const int (&na)[NEN], m3 &K,
                                              double &detJ, double &r)
 {
     m3 J;
-    grad_field<ELEM, Q>(sX, na, J);
+    grad_field<ELEM, Q, NEN, REL>(sX, na, J);
     cofactor(J, K);
     detJ = det_from_cof(J, K);
     r = 1.0 / detJ;
@@ -546,33 +560,38 @@ __device__ __forceinline__ Mat load_mat(const BlockDesc &b, const double *__rest
 
 // Offsets (in doubles) of the staged fields inside one LDS node record.
 // X and x always; the adjoint adds w, the tangent dx; damped blocks add v
-// (and the tangent dv).
-template <int OP, bool DAMPED>
+// (and the tangent dv).  The step residual (forward, kModeStep) adds
+// u = v - v_n last; the Newton operator (tangent, kModeStep) keeps the
+// tangent's layout with dx = h dv.
+template <int OP, bool DAMPED, int MODE = kModePlain>
 struct Rec {
     static constexpr bool has2 = OP != kOpFwd;              // w or dx
     static constexpr bool hasdv = DAMPED && OP == kOpJvp;
     static constexpr int oX = 0, ox = 3, o2 = 6;
     static constexpr int ov = has2 ? 9 : 6;
     static constexpr int odv = ov + 3;
-    static constexpr int nfield = record_fields_len(OP, DAMPED) / 3;   // staged fields
-    static constexpr int len = record_len(OP, DAMPED);                  // stride (odd)
-    static_assert(3 * nfield == 6 + (has2 ? 3 : 0) + (DAMPED ? 3 : 0) + (hasdv ? 3 : 0), "record layout");
+    static constexpr int ou = DAMPED ? ov + 3 : ov;          // step residual: v - v_n
+    static constexpr int nfield = record_fields_len(OP, DAMPED, MODE) / 3;   // staged fields
+    static constexpr int len = record_len(OP, DAMPED, MODE);                  // stride (odd)
+    static_assert(3 * nfield == 6 + (has2 ? 3 : 0) + (DAMPED ? 3 : 0) + (hasdv ? 3 : 0) +
+                                    ((OP == kOpFwd && MODE == kModeStep) ? 3 : 0),
+                  "record layout");
 };
 
 // Forward: fe[a] = sum_q w_q J_p P(F_q, Fdot_q) h_a   (Sec. 4.3 with Sec. 6)
-template <int ELEM, int LAW, bool DAMPED, int NEN>
+template <int ELEM, int LAW, bool DAMPED, int MODE, int NEN>
 __device__ __forceinline__ void fwd_element(const double *sm, const int (&na)[NEN], const Mat &mt,
                                             double (&fe)[NEN][3])
 {
     using E = ElemDef<ELEM>;
-    using R = Rec<kOpFwd, DAMPED>;
+    using R = Rec<kOpFwd, DAMPED, MODE>;
     point_loop<E::nq>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         qp_fence();
         m3 K, G, F, Fd, P, Qm;
         double detJ, r;
-        ref_geometry<ELEM, q>(sm + R::oX, na, K, detJ, r);
-        grad_field<ELEM, q>(sm + R::ox, na, G);
+        ref_geometry<ELEM, q, NEN, true>(sm + R::oX, na, K, detJ, r);
+        grad_field<ELEM, q, NEN, true>(sm + R::ox, na, G);
         to_reference(G, K, r, F);                   // F = N H
         if constexpr (DAMPED) {
             grad_field<ELEM, q>(sm + R::ov, na, G);
@@ -600,12 +619,17 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpVjp, DAMPED>;
+    // The parameter gradients are stress-like (they cancel F against the
+    // rotation as the stress does): positions relative to each element's
+    // first node there.  The H8 adjoint keeps tile-relative positions (with
+    // them its schedule spills hundreds of registers).
+    constexpr bool REL = WANT_GT && ELEM == kT10;
     point_loop<E::nq>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         m3 K, G, F, Gw, Fb;
         double detJ, r;
-        ref_geometry<ELEM, q>(sm + R::oX, na, K, detJ, r);
-        grad_field<ELEM, q>(sm + R::ox, na, G);
+        ref_geometry<ELEM, q, NEN, REL>(sm + R::oX, na, K, detJ, r);
+        grad_field<ELEM, q, NEN, REL>(sm + R::ox, na, G);
         to_reference(G, K, r, F);
         grad_field<ELEM, q>(sm + R::o2, na, G);
         to_reference(G, K, r, Gw);
@@ -663,7 +687,7 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
         {
             m3 K2;
             double d2, r2;
-            ref_geometry<ELEM, q>(sm + R::oX, na, K2, d2, r2);
+            ref_geometry<ELEM, q, NEN, REL>(sm + R::oX, na, K2, d2, r2);
             to_parent(Fb, K2, E::weight(q), Qm);
         }
         scatter_grad<ELEM, q, NEN, DAMPED ? 1 : 0>(Qm, gx);
@@ -675,10 +699,11 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
 }
 
 // Tangent: dF = sum_a dx_a h_a^T, dFdot = sum_a dv_a h_a^T,
-//   dP = (dP_e/dF)[dF] + dF S_v + F S_v[sym(dF^T Fdot + F^T dFdot)],
+//   dP = (dP_e/dF)[dF] + dF S_v + F S_v[sym(dF^T Fdot + F^T dFdot)]
+//        (+ P(F, Fdot; dtheta) when DT: the stress is linear in the parameters),
 //   df_a += c_q dP h_a.
-template <int ELEM, int LAW, bool DAMPED, int NEN>
-__device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NEN], const Mat &mt,
+template <int ELEM, int LAW, bool DAMPED, bool DT, int NEN>
+__device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NEN], const Mat &mt, const Mat &dmt,
                                             double (&df)[NEN][3])
 {
     using E = ElemDef<ELEM>;
@@ -702,6 +727,13 @@ __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NE
             m3 Fd, Ed, Sv, A, B, T;
             grad_field<ELEM, q>(sm + R::ov, na, G);
             to_reference(G, K, r, Fd);
+            if constexpr (DT) {
+                stress<LAW, true>(F, Fd, dmt, T);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) dP[i][j] += T[i][j];
+            }
             sym_FtG(F, Fd, Ed);
             visc_op(mt, Ed, Sv);
             mm(dF, Sv, T);
@@ -730,10 +762,56 @@ __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NE
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) dP[i][j] += T[i][j];
+        } else if constexpr (DT) {
+            m3 T;
+            stress<LAW, false>(F, F, dmt, T);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dP[i][j] += T[i][j];
         }
         m3 Qm;
         to_parent(dP, K, E::weight(q), Qm);
         scatter_grad<ELEM, q>(Qm, df);
+    });
+}
+
+// Consistent-mass action of one element (Sec. 4.1): fe[a] += scale
+// sum_q c_q s_a(xi_q) sum_b s_b(xi_q) u_b, with c_q = rho w_q J_p(xi_q)
+// precomputed per element (coef, stride n_elem between points) and the
+// mass rule's shape values compile-time constants.  su points at the u
+// field of the node records.
+template <int ELEM, int NEN>
+__device__ __forceinline__ void mass_element(const double *su, const int (&na)[NEN], const double *coef,
+                                             int64_t stride, double scale, double (&fe)[NEN][3])
+{
+    using M = MassRule<ELEM>;
+    point_loop<M::nq>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        qp_fence();
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+        static_for<NEN>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+            constexpr double sb = M::shape(q, b);
+            if constexpr (sb != 0.0) {
+                u0 += sb * su[na[b]];
+                u1 += sb * su[na[b] + 1];
+                u2 += sb * su[na[b] + 2];
+            }
+        });
+        const double cq = __builtin_nontemporal_load(coef + q * stride) * scale;
+        u0 *= cq;
+        u1 *= cq;
+        u2 *= cq;
+        static_for<NEN>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            constexpr double sa = M::shape(q, a);
+            if constexpr (sa != 0.0) {
+                fe[a][0] += sa * u0;
+                fe[a][1] += sa * u1;
+                fe[a][2] += sa * u2;
+            }
+        });
     });
 }
 
@@ -751,17 +829,27 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return t < n ? t : -1;
 }
 
-// Global source of field f of the LDS node record (record order x, then w
-// or dx, then v, then dv; X comes from the mesh's tile records); null
-// operands (dx or dv of the tangent) read as 0.
-template <int OP, bool DAMPED>
-__device__ __forceinline__ const double *field_src(int f, const CallArgs &c)
+// Value staged for field f (record order: x, then w or dx, then v, then
+// dv; the step residual's u = v - v_n last; X comes from the mesh's tile
+// records), component cc, global node g; null operands (dx or dv of the
+// tangent) read as 0.  In the step modes the positions are the step map
+// q = q_n + h v, formed with one rounding (a fused multiply-add) so that
+// every node's value, and its difference to the tile's reference node,
+// is the same in every call; the Newton operator's dx is h dv.
+template <int OP, bool DAMPED, int MODE>
+__device__ __forceinline__ double field_value(int f, int cc, int64_t g, const CallArgs &c, int64_t n)
 {
-    using R = Rec<OP, DAMPED>;
-    if (f == R::ox / 3) return c.x;
-    if (R::has2 && f == R::o2 / 3) return OP == kOpVjp ? c.w : c.dx;
-    if (DAMPED && f == R::ov / 3) return c.v;
-    return c.dv;
+    using R = Rec<OP, DAMPED, MODE>;
+    const int64_t i = cc * n + g;
+    if (f == R::ox / 3) return MODE == kModeStep ? __builtin_fma(c.h, c.v[i], c.qn[i]) : c.x[i];
+    if (R::has2 && f == R::o2 / 3) {
+        if (OP == kOpVjp) return c.w[i];
+        if (MODE == kModeStep) return c.h * c.dv[i];
+        return c.dx ? c.dx[i] : 0.0;
+    }
+    if (OP == kOpFwd && MODE == kModeStep && f == R::ou / 3) return c.v[i] - c.vn[i];
+    if (DAMPED && f == R::ov / 3) return c.v[i];
+    return c.dv ? c.dv[i] : 0.0;
 }
 
 // Stage the tile's node records.  The host caps a tile at kStagePerThread x
@@ -772,18 +860,24 @@ __device__ __forceinline__ const double *field_src(int f, const CallArgs &c)
 // gradients of an element sum to zero), and coordinates of the size of a
 // tile instead of the size of the body keep the per-point gradient sums free
 // of cancellation.  The reference part is read contiguously from the mesh,
-// which stores it per tile node already relative to the tile's reference node;
-// the other fields are gathered from the caller's [3][n] arrays.  The mesh's
+// which stores it per tile node relative to the tile's reference node in
+// every component where that subtraction is exact for all the tile's nodes
+// (and as is elsewhere, where the coordinates are within a few tile widths
+// of zero); the other fields are gathered from the caller's [3][n] arrays.
+// RAW kernels, which difference positions per element (the REL forms below),
+// stage the current positions as they are: the per-element difference of
+// raw coordinates is then rounded once, where a difference of two
+// tile-relative values near zero would carry the rounding of both.  The mesh's
 // per-tile arrays are read once per call and are loaded non-temporally, which
 // leaves the L2 to the node data that neighbouring tiles share.  The nodes
 // are read in the tile's sorted node order (coalesced) and each record goes
 // to the node's LDS position, which the host chose to spread the per-point
 // gathers of a wavefront over the LDS banks.
-template <int OP, bool DAMPED>
+template <int OP, bool DAMPED, int MODE = kModePlain, bool RAW = false>
 __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMesh &m, const CallArgs &c,
                                            const TileDesc &t, int tid, int nthr)
 {
-    using R = Rec<OP, DAMPED>;
+    using R = Rec<OP, DAMPED, MODE>;
     constexpr int nf = R::nfield;
     const int32_t *gid = m.lnode_gid + t.node_begin;
     const uint16_t *lpos = m.lnode_pos + t.node_begin;
@@ -806,14 +900,13 @@ __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMes
     }
 #pragma unroll
     for (int f = 1; f < nf; ++f) {
-        const double *p = field_src<OP, DAMPED>(f, c);
-        const bool centre = f == R::ox / 3;
+        const bool centre = !RAW && f == R::ox / 3;
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
-            const double o = centre ? p[cc * n + g0] : 0.0;
+            const double o = centre ? field_value<OP, DAMPED, MODE>(f, cc, g0, c, n) : 0.0;
 #pragma unroll
             for (int k = 0; k < kStagePerThread; ++k)
-                v[k][3 * f + cc] = (p && g[k] >= 0) ? p[cc * n + g[k]] - o : 0.0;
+                v[k][3 * f + cc] = g[k] >= 0 ? field_value<OP, DAMPED, MODE>(f, cc, g[k], c, n) - o : 0.0;
         }
     }
 #pragma unroll
@@ -906,7 +999,8 @@ __device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, co
 template <int NC>
 __device__ __forceinline__ void reduce_components(const DevMesh &m, const TileDesc &t, const TileCsr &c,
                                                   const double *__restrict__ slot, int slot_stride,
-                                                  double *__restrict__ out, int field, int r0, int tid, int nthr)
+                                                  double *__restrict__ out, const double *__restrict__ sub,
+                                                  int field, int r0, int tid, int nthr)
 {
     constexpr int U = 8;
     for (int l = tid; l < t.n_node; l += nthr) {
@@ -928,8 +1022,12 @@ __device__ __forceinline__ void reduce_components(const DevMesh &m, const TileDe
         const int d = c.dst[l];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            if (d >= 0) out[(r0 + k) * m.n_nodes + d] = s[k];
-            else m.part[(int64_t)(3 * field + r0 + k) * m.n_part + (-1 - d)] = s[k];
+            if (d >= 0) {
+                const int64_t o = (r0 + k) * m.n_nodes + d;
+                out[o] = sub ? s[k] - sub[o] : s[k];
+            } else {
+                m.part[(int64_t)(3 * field + r0 + k) * m.n_part + (-1 - d)] = s[k];
+            }
         }
     }
 }
@@ -941,7 +1039,8 @@ __device__ __forceinline__ void reduce_components(const DevMesh &m, const TileDe
 template <int NEN, int NC>
 __device__ __forceinline__ void assemble_nc(const DevMesh &m, const TileDesc &t, const TileCsr &c,
                                             double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
-                                            double *__restrict__ out, int field, int tid, int te)
+                                            double *__restrict__ out, const double *__restrict__ sub, int field,
+                                            int tid, int te)
 {
     const int stride = NEN * te;
 #pragma unroll
@@ -956,19 +1055,20 @@ __device__ __forceinline__ void assemble_nc(const DevMesh &m, const TileDesc &t,
                 }
         }
         __syncthreads();
-        if (r0 + NC <= 3) reduce_components<NC>(m, t, c, sm, stride, out, field, r0, tid, te);
-        else reduce_components<(3 % NC) ? (3 % NC) : 1>(m, t, c, sm, stride, out, field, r0, tid, te);
+        if (r0 + NC <= 3) reduce_components<NC>(m, t, c, sm, stride, out, sub, field, r0, tid, te);
+        else reduce_components<(3 % NC) ? (3 % NC) : 1>(m, t, c, sm, stride, out, sub, field, r0, tid, te);
     }
 }
 
 template <int NEN>
 __device__ __forceinline__ void assemble(const DevMesh &m, const TileDesc &t, const TileCsr &c,
                                          double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
-                                         double *__restrict__ out, int field, int tid, int te, int nc)
+                                         double *__restrict__ out, int field, int tid, int te, int nc,
+                                         const double *__restrict__ sub = nullptr)
 {
-    if (nc >= 3) assemble_nc<NEN, 3>(m, t, c, sm, fe, active, out, field, tid, te);
-    else if (nc == 2) assemble_nc<NEN, 2>(m, t, c, sm, fe, active, out, field, tid, te);
-    else assemble_nc<NEN, 1>(m, t, c, sm, fe, active, out, field, tid, te);
+    if (nc >= 3) assemble_nc<NEN, 3>(m, t, c, sm, fe, active, out, sub, field, tid, te);
+    else if (nc == 2) assemble_nc<NEN, 2>(m, t, c, sm, fe, active, out, sub, field, tid, te);
+    else assemble_nc<NEN, 1>(m, t, c, sm, fe, active, out, sub, field, tid, te);
 }
 
 // Zeros for every destination of the tile's nodes (an undamped tile's share
@@ -992,11 +1092,15 @@ __device__ __forceinline__ void zero_nodes(const DevMesh &m, const TileDesc &t, 
 
 
 
-template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpFwd, ELEM, LAW, DAMPED)))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
+// The forward internal force (MODE plain), or the backward-Euler step
+// residual without constraints (MODE step, Sec. 7): positions q = q_n + h v,
+// g = f_int(q, v) + M (v - v_n) / h - f_ext, the inertia term from the
+// consistent mass (Sec. 4.1) and f_ext subtracted at every node's store.
+template <int ELEM, int LAW, bool DAMPED, int MODE>
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpFwd, ELEM, LAW, DAMPED, MODE)))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
-    using R = Rec<kOpFwd, DAMPED>;
+    using R = Rec<kOpFwd, DAMPED, MODE>;
     extern __shared__ double smem[];
     const int ti = xcd_tile(blockIdx.x, ntile);
     if (ti < 0) return;
@@ -1007,7 +1111,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
     stage_csr<NEN>(csr, m, t, tid, te);
-    stage_tile<kOpFwd, DAMPED>(smem, m, c, t, tid, te);
+    stage_tile<kOpFwd, DAMPED, MODE, true>(smem, m, c, t, tid, te);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double fe[NEN][3];
@@ -1019,9 +1123,12 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
         load_na<NEN, R::len>(m, t, tid, te, na);
         const int uid = m.elem_uid[t.elem_begin + tid];
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
-        fwd_element<ELEM, LAW, DAMPED>(smem, na, mt, fe);
+        fwd_element<ELEM, LAW, DAMPED, MODE>(smem, na, mt, fe);
+        if constexpr (MODE == kModeStep)
+            if (m.mass_c)
+                mass_element<ELEM>(smem + R::ou, na, m.mass_c + t.elem_begin + tid, m.n_elem, 1.0 / c.h, fe);
     }
-    assemble<NEN>(m, t, csr, smem, fe, active, c.out0, 0, tid, te, nc);
+    assemble<NEN>(m, t, csr, smem, fe, active, c.out0, 0, tid, te, nc, MODE == kModeStep ? c.sub : nullptr);
 }
 
 // Two waves per SIMD (256 registers); the damped Mooney-Rivlin adjoint, which
@@ -1042,7 +1149,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
     stage_csr<NEN>(csr, m, t, tid, te);
-    stage_tile<kOpVjp, DAMPED>(smem, m, c, t, tid, te);
+    stage_tile<kOpVjp, DAMPED, kModePlain, WANT_GT && ELEM == kT10>(smem, m, c, t, tid, te);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double gx[NEN][3], gv[NEN][3], gt[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1074,15 +1181,18 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
 }
 
 // The tangent stages dx (zeros when null) and, for damped blocks, dv (zeros
-// when null), so one instantiation serves every combination.  At least two
-// waves per SIMD: left free, the compiler gave the Mooney-Rivlin tangent one
-// wave and 512 registers, which ran about 20 % slower than two waves with a
-// small spill.
-template <int ELEM, int LAW, bool DAMPED>
-__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpJvp, ELEM, LAW, DAMPED)))) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
+// when null), so one instantiation serves every combination; DT adds the
+// parameter direction dtheta.  At least two waves per SIMD: left free, the
+// compiler gave the Mooney-Rivlin tangent one wave and 512 registers, which
+// ran about 20 % slower than two waves with a small spill.
+// MODE step: the Newton operator of the step residual (Sec. 7),
+// y = (M / h + h K + C) dv at q = q_n + h v: the tangent with dx = h dv and
+// the inertia term M (h dv) / h^2 from the consistent mass (Sec. 4.1).
+template <int ELEM, int LAW, bool DAMPED, bool DT, int MODE>
+__global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpJvp, ELEM, LAW, DAMPED, MODE)))) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
-    using R = Rec<kOpJvp, DAMPED>;
+    using R = Rec<kOpJvp, DAMPED, MODE>;
     extern __shared__ double smem[];
     const int ti = xcd_tile(blockIdx.x, ntile);
     if (ti < 0) return;
@@ -1093,7 +1203,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
     stage_csr<NEN>(csr, m, t, tid, te);
-    stage_tile<kOpJvp, DAMPED>(smem, m, c, t, tid, te);
+    stage_tile<kOpJvp, DAMPED, MODE>(smem, m, c, t, tid, te);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double df[NEN][3];
@@ -1105,9 +1215,61 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
         load_na<NEN, R::len>(m, t, tid, te, na);
         const int uid = m.elem_uid[t.elem_begin + tid];
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
-        jvp_element<ELEM, LAW, DAMPED>(smem, na, mt, df);
+        Mat dmt{};
+        if constexpr (DT) dmt = load_mat<LAW>(m.blocks[t.block], c.dtheta, m.n_elem, uid, DAMPED);
+        jvp_element<ELEM, LAW, DAMPED, DT>(smem, na, mt, dmt, df);
+        if constexpr (MODE == kModeStep)
+            if (m.mass_c)
+                mass_element<ELEM>(smem + R::o2, na, m.mass_c + t.elem_begin + tid, m.n_elem, 1.0 / (c.h * c.h), df);
     }
     assemble<NEN>(m, t, csr, smem, df, active, c.out0, 0, tid, te, nc);
+}
+
+// Consistent-mass action y = M u (Sec. 4.1): the tile stages u only.
+template <int ELEM>
+__global__ __launch_bounds__(TLFEA_MAX_TE) void k_mass(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
+{
+    constexpr int NEN = ElemDef<ELEM>::nen;
+    constexpr int LEN = record_len(kOpMass, false);
+    extern __shared__ double smem[];
+    const int ti = xcd_tile(blockIdx.x, ntile);
+    if (ti < 0) return;
+    const TileDesc t = m.tiles[tile0 + ti];
+    const int tid = threadIdx.x;
+    const TileCsr csr = csr_layout(smem, nl, LEN, NEN, te, nc);
+    stage_csr<NEN>(csr, m, t, tid, te);
+    {
+        const int32_t *gid = m.lnode_gid + t.node_begin;
+        const uint16_t *lpos = m.lnode_pos + t.node_begin;
+        int g[kStagePerThread], p[kStagePerThread];
+        double v[kStagePerThread][3];
+#pragma unroll
+        for (int k = 0; k < kStagePerThread; ++k) {
+            const int l = tid + k * te;
+            g[k] = l < t.n_node ? __builtin_nontemporal_load(gid + l) : -1;
+            p[k] = l < t.n_node ? (int)__builtin_nontemporal_load(lpos + l) : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kStagePerThread; ++k)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) v[k][cc] = g[k] >= 0 ? c.x[cc * m.n_nodes + g[k]] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kStagePerThread; ++k)
+            if (g[k] >= 0)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) smem[p[k] * LEN + cc] = v[k][cc];
+    }
+    __syncthreads();
+    double fe[NEN][3];
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) fe[a][0] = fe[a][1] = fe[a][2] = 0.0;
+    const bool active = tid < t.n_elem;
+    if (active && m.mass_c) {
+        int na[NEN];
+        load_na<NEN, LEN>(m, t, tid, te, na);
+        mass_element<ELEM>(smem, na, m.mass_c + t.elem_begin + tid, m.n_elem, 1.0, fe);
+    }
+    assemble<NEN>(m, t, csr, smem, fe, active, c.out0, 0, tid, te, nc);
 }
 
 // Quadrature points with det F <= 0 (inverted or collapsed there).  The
@@ -1128,7 +1290,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_inverted(DevMesh m, CallArgs c
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
-    stage_tile<kOpFwd, false>(smem, m, c, t, tid, te);
+    stage_tile<kOpFwd, false, kModePlain, true>(smem, m, c, t, tid, te);
     __syncthreads();
     int n = 0;
     if (tid < t.n_elem) {
@@ -1138,8 +1300,8 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_inverted(DevMesh m, CallArgs c
             constexpr int q = decltype(qc)::value;
             m3 K, G, F, cof;
             double detJ, r;
-            ref_geometry<ELEM, q>(smem + R::oX, na, K, detJ, r);
-            grad_field<ELEM, q>(smem + R::ox, na, G);
+            ref_geometry<ELEM, q, NEN, true>(smem + R::oX, na, K, detJ, r);
+            grad_field<ELEM, q, NEN, true>(smem + R::ox, na, G);
             to_reference(G, K, r, F);
             cofactor(F, cof);
             n += det_from_cof(F, cof) <= 0.0 ? 1 : 0;
@@ -1161,24 +1323,30 @@ hipError_t launch_inverted_class(int te, int n_tiles, size_t lds, hipStream_t s,
     return hipGetLastError();
 }
 
-template <int OP, int ELEM, int LAW, bool DAMPED, int GT>
+template <int OP, int ELEM, int LAW, bool DAMPED, int GT, int MODE>
 hipError_t launch_one(dim3 grid, int te, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c, int tile0,
                       int ntile, int nl, int nc)
 {
-    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED, MODE><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     else if constexpr (OP == kOpVjp) {
         // one adjoint translation unit per gtheta choice (each with the
         // instruction scheduler that suits it); the host picks the unit
         if ((c.gtheta != nullptr) != (GT != 0)) return hipErrorInvalidValue;
         k_vjp<ELEM, LAW, DAMPED, GT != 0><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+    } else if constexpr (MODE == kModeStep) {
+        k_jvp<ELEM, LAW, DAMPED, false, kModeStep><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+    } else {
+        if (c.dtheta) k_jvp<ELEM, LAW, DAMPED, true, kModePlain><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+        else k_jvp<ELEM, LAW, DAMPED, false, kModePlain><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     }
-    else k_jvp<ELEM, LAW, DAMPED><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     return hipGetLastError();
 }
 
 // GT: which adjoint a unit instantiates (part of the template arguments, so
-// that the two adjoint units' launchers are distinct functions)
-template <int OP, int ELEM, int GT>
+// that the two adjoint units' launchers are distinct functions); MODE: the
+// plain operation or its step variant (forward: step residual, tangent:
+// Newton operator).
+template <int OP, int ELEM, int GT, int MODE>
 hipError_t launch_class(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m,
                         const CallArgs &c, int tile0, int nl, int nc)
 {
@@ -1186,14 +1354,25 @@ hipError_t launch_class(int law, int damped, int te, int n_tiles, size_t lds, hi
     if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
     switch (law * 2 + (damped ? 1 : 0)) {
-    case 0: return launch_one<OP, ELEM, 0, false, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 1: return launch_one<OP, ELEM, 0, true, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 2: return launch_one<OP, ELEM, 1, false, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 3: return launch_one<OP, ELEM, 1, true, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 4: return launch_one<OP, ELEM, 2, false, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
-    case 5: return launch_one<OP, ELEM, 2, true, GT>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 0: return launch_one<OP, ELEM, 0, false, GT, MODE>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 1: return launch_one<OP, ELEM, 0, true, GT, MODE>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 2: return launch_one<OP, ELEM, 1, false, GT, MODE>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 3: return launch_one<OP, ELEM, 1, true, GT, MODE>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 4: return launch_one<OP, ELEM, 2, false, GT, MODE>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
+    case 5: return launch_one<OP, ELEM, 2, true, GT, MODE>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int ELEM>
+hipError_t launch_mass_class(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
+                             int tile0, int nl, int nc)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
+    k_mass<ELEM><<<grid, te, lds, s>>>(m, c, tile0, n_tiles, te, nl, nc);
+    return hipGetLastError();
 }
 
 }  // namespace tlfea

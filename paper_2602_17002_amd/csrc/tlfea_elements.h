@@ -50,6 +50,25 @@ template <> struct ElemDef<kT10> {
     {
         return grad_at(a, k, qp(q, 0), qp(q, 1), qp(q, 2));
     }
+    // s_a at parent point (x, y, z): the paper's shape functions of App. A
+    // (10-node tetrahedron), written through the barycentric coordinate
+    // l = 1 - x - y - z of the first corner
+    static constexpr TLFEA_HD double shape_at(int a, double x, double y, double z)
+    {
+        const double l = 1.0 - x - y - z;
+        switch (a) {
+        case 0: return l * (2 * l - 1);
+        case 1: return x * (2 * x - 1);
+        case 2: return y * (2 * y - 1);
+        case 3: return z * (2 * z - 1);
+        case 4: return 4 * x * l;
+        case 5: return 4 * x * y;
+        case 6: return 4 * y * l;
+        case 7: return 4 * z * l;
+        case 8: return 4 * x * z;
+        default: return 4 * y * z;
+        }
+    }
     // corners used to decide whether the parent-to-reference map is affine
     static constexpr int n_corner = 4;
 };
@@ -74,7 +93,61 @@ template <> struct ElemDef<kH8> {
     {
         return grad_at(a, k, qp(q, 0), qp(q, 1), qp(q, 2));
     }
+    static constexpr TLFEA_HD double shape_at(int a, double x, double y, double z)
+    {
+        return 0.125 * (1.0 + sgn(a, 0) * x) * (1.0 + sgn(a, 1) * y) * (1.0 + sgn(a, 2) * z);
+    }
     static constexpr int n_corner = 8;
+};
+
+// Quadrature of the consistent mass m_ij = int rho s_i s_j dV_r (Sec. 4.1),
+// exact with positive weights for the integrand of straight-sided elements
+// (twice the shape functions' degree), so the element mass matrix is the
+// exact Gram matrix there.  T10: the 15-point degree-5 rule of Hammer,
+// Marlowe and Stroud (barycentric orbits: the centroid; (a, a, a, 1 - 3a)
+// for a = (7 -+ sqrt 15) / 34; (b, b, 1/2 - b, 1/2 - b) for
+// b = (5 - sqrt 15) / 20), weights 16/135, (2665 +- 14 sqrt 15) / 37800 and
+// 10/189 of the parent volume 1/6.  H8: the 2x2x2 Gauss rule.
+template <int ELEM> struct MassRule;
+
+template <> struct MassRule<kT10> {
+    static constexpr int nq = 15;
+    static constexpr double r15 = 3.8729833462074168851792653997823996108;   // sqrt(15)
+    static constexpr double a1 = (7.0 - r15) / 34.0, a2 = (7.0 + r15) / 34.0;
+    static constexpr double b = (5.0 - r15) / 20.0, c = 0.5 - b;
+    // barycentric coordinate k (0..3) of point q; the parent coordinates
+    // (xi, eta, zeta) are the barycentric coordinates 1..3
+    static constexpr TLFEA_HD double bary(int q, int k)
+    {
+        if (q == 0) return 0.25;
+        if (q <= 8) {
+            const double a = q <= 4 ? a1 : a2;
+            return k == (q - 1) % 4 ? 1.0 - 3.0 * a : a;
+        }
+        // pairs (i, j), i < j, in the order (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+        constexpr int pi[6] = {0, 0, 0, 1, 1, 2}, pj[6] = {1, 2, 3, 2, 3, 3};
+        return (k == pi[q - 9] || k == pj[q - 9]) ? b : c;
+    }
+    static constexpr TLFEA_HD double qp(int q, int k) { return bary(q, k + 1); }
+    static constexpr TLFEA_HD double weight(int q)
+    {
+        return (q == 0 ? 16.0 / 135.0
+                       : q <= 4 ? (2665.0 + 14.0 * r15) / 37800.0
+                                : q <= 8 ? (2665.0 - 14.0 * r15) / 37800.0 : 10.0 / 189.0) / 6.0;
+    }
+    static constexpr TLFEA_HD double shape(int q, int a) { return ElemDef<kT10>::shape_at(a, qp(q, 0), qp(q, 1), qp(q, 2)); }
+    static constexpr TLFEA_HD double grad(int q, int a, int k)
+    {
+        return ElemDef<kT10>::grad_at(a, k, qp(q, 0), qp(q, 1), qp(q, 2));
+    }
+};
+
+template <> struct MassRule<kH8> {
+    static constexpr int nq = 8;
+    static constexpr TLFEA_HD double qp(int q, int k) { return ElemDef<kH8>::qp(q, k); }
+    static constexpr TLFEA_HD double weight(int q) { return ElemDef<kH8>::weight(q); }
+    static constexpr TLFEA_HD double shape(int q, int a) { return ElemDef<kH8>::shape_at(a, qp(q, 0), qp(q, 1), qp(q, 2)); }
+    static constexpr TLFEA_HD double grad(int q, int a, int k) { return ElemDef<kH8>::grad(q, a, k); }
 };
 
 }  // namespace tlfea

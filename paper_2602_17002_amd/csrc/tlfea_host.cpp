@@ -6,9 +6,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -17,38 +19,76 @@
 #include "tlfea.h"
 #include "tlfea_elements.h"
 #include "tlfea_internal.h"
+#include "tlfea_joints.h"
 
 namespace tlfea {
-#define TLFEA_DECL(e, o)                                                                                   \
-    hipError_t launch_tiles_e##e##_o##o(int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, \
-                                        const DevMesh &m, const CallArgs &c, int tile0, int nl, int nc);
-TLFEA_DECL(0, 0)
-TLFEA_DECL(0, 1_g0)
-TLFEA_DECL(0, 1_g1)
-TLFEA_DECL(0, 2)
-TLFEA_DECL(1, 0)
-TLFEA_DECL(1, 1_g0)
-TLFEA_DECL(1, 1_g1)
-TLFEA_DECL(1, 2)
+#define TLFEA_DECL(e, o, g, md)                                                                               \
+    hipError_t launch_tiles_e##e##_o##o##_g##g##_m##md(int law, int damped, int te, int n_tiles, size_t lds,     \
+                                                       hipStream_t s, const DevMesh &m, const CallArgs &c,       \
+                                                       int tile0, int nl, int nc);
+TLFEA_DECL(0, 0, 0, 0) TLFEA_DECL(0, 0, 0, 1) TLFEA_DECL(0, 1, 0, 0) TLFEA_DECL(0, 1, 1, 0)
+TLFEA_DECL(0, 2, 0, 0) TLFEA_DECL(0, 2, 0, 1)
+TLFEA_DECL(1, 0, 0, 0) TLFEA_DECL(1, 0, 0, 1) TLFEA_DECL(1, 1, 0, 0) TLFEA_DECL(1, 1, 1, 0)
+TLFEA_DECL(1, 2, 0, 0) TLFEA_DECL(1, 2, 0, 1)
 #undef TLFEA_DECL
-hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1);
+hipError_t launch_mass_e0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
+                          int tile0, int nl, int nc);
+hipError_t launch_mass_e1(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
+                          int tile0, int nl, int nc);
+hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1, const double *sub);
 hipError_t launch_inverted_e0_o0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
                                  int tile0, unsigned long long *count);
 hipError_t launch_inverted_e1_o0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
                                  int tile0, unsigned long long *count);
 hipError_t launch_zero_count(hipStream_t s, unsigned long long *count);
+// vector kernels of the Newton-Krylov step (tlfea_vec.hip)
+constexpr int kDotBlocks = 256, kVecChunk = 8;
+hipError_t launch_mdot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *partial,
+                       hipStream_t s);
+hipError_t launch_maxpy(const double *V, int64_t ldv, int nvec, const double *c, double *y, int64_t n, hipStream_t s);
+hipError_t launch_axpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t s);
+hipError_t launch_add(const double *x, const double *y, double *z, int64_t n, hipStream_t s);
+// joint kernels (tlfea_joints.hip)
+hipError_t launch_joints(const DevJoints &J, const double *q, const double *lambda, double rho, double h,
+                         double *c_out, int want_z, hipStream_t s);
+hipError_t launch_joint_scatter(const DevJoints &J, double *out, int accumulate, hipStream_t s);
 
-static hipError_t launch_tiles(int elem, int law, int damped, int te, int op, int n_tiles, size_t lds, hipStream_t s,
+// What one call runs over the tiles: the operation of the kernels and its
+// variant.  Also the kernel-timing ids of the tile launches (with 3 = the
+// shared-node sums and 4 = a batched graph replay in between).
+enum Kind { kKFwd = 0, kKVjp = 1, kKJvp = 2, kKRes = 5, kKNewt = 6, kKMass = 7 };
+constexpr int kKinds[] = {kKFwd, kKVjp, kKJvp, kKRes, kKNewt, kKMass};
+constexpr int kind_slot(int kind) { return kind <= kKJvp ? kind : kind - 2; }   // 0..5
+constexpr int kind_op(int kind)
+{
+    return kind == kKRes ? kOpFwd : kind == kKNewt ? kOpJvp : kind == kKMass ? kOpMass : kind;
+}
+constexpr int kind_mode(int kind) { return (kind == kKRes || kind == kKNewt) ? kModeStep : kModePlain; }
+
+static hipError_t launch_tiles(int elem, int law, int damped, int te, int kind, int n_tiles, size_t lds, hipStream_t s,
                                const DevMesh &m, const CallArgs &c, int tile0, int nl, int nc)
 {
     typedef hipError_t (*fn_t)(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int,
                                int);
-    // the adjoint has one unit without and one with the parameter gradients
-    static const fn_t table[2][4] = {
-        {launch_tiles_e0_o0, launch_tiles_e0_o1_g0, launch_tiles_e0_o2, launch_tiles_e0_o1_g1},
-        {launch_tiles_e1_o0, launch_tiles_e1_o1_g0, launch_tiles_e1_o2, launch_tiles_e1_o1_g1}};
-    if (elem < 0 || elem > 1 || op < 0 || op > 2) return hipErrorInvalidValue;
-    const int k = (op == kOpVjp && c.gtheta) ? 3 : op;
+    // per element type: forward, adjoint, tangent, step residual, Newton
+    // operator, and the adjoint with the parameter gradients
+    static const fn_t table[2][6] = {
+        {launch_tiles_e0_o0_g0_m0, launch_tiles_e0_o1_g0_m0, launch_tiles_e0_o2_g0_m0, launch_tiles_e0_o0_g0_m1,
+         launch_tiles_e0_o2_g0_m1, launch_tiles_e0_o1_g1_m0},
+        {launch_tiles_e1_o0_g0_m0, launch_tiles_e1_o1_g0_m0, launch_tiles_e1_o2_g0_m0, launch_tiles_e1_o0_g0_m1,
+         launch_tiles_e1_o2_g0_m1, launch_tiles_e1_o1_g1_m0}};
+    if (elem < 0 || elem > 1) return hipErrorInvalidValue;
+    if (kind == kKMass)
+        return (elem == 0 ? launch_mass_e0 : launch_mass_e1)(te, n_tiles, lds, s, m, c, tile0, nl, nc);
+    int k;
+    switch (kind) {
+    case kKFwd: k = 0; break;
+    case kKVjp: k = c.gtheta ? 5 : 1; break;
+    case kKJvp: k = 2; break;
+    case kKRes: k = 3; break;
+    case kKNewt: k = 4; break;
+    default: return hipErrorInvalidValue;
+    }
     return table[elem][k](law, damped, te, n_tiles, lds, s, m, c, tile0, nl, nc);
 }
 }  // namespace tlfea
@@ -89,6 +129,23 @@ static double grad_of(int elem, int q, int a, int k)
 {
     return elem == kT10 ? ElemDef<kT10>::grad(q, a, k) : ElemDef<kH8>::grad(q, a, k);
 }
+static double shape_of(int elem, int a, const double *xi)
+{
+    return elem == kT10 ? ElemDef<kT10>::shape_at(a, xi[0], xi[1], xi[2]) : ElemDef<kH8>::shape_at(a, xi[0], xi[1], xi[2]);
+}
+static double weight_of(int elem, int q)
+{
+    return elem == kT10 ? ElemDef<kT10>::weight(q) : ElemDef<kH8>::weight(q);
+}
+static int nqm_of(int elem) { return elem == kT10 ? MassRule<kT10>::nq : MassRule<kH8>::nq; }
+static double mass_weight_of(int elem, int q)
+{
+    return elem == kT10 ? MassRule<kT10>::weight(q) : MassRule<kH8>::weight(q);
+}
+static double mass_grad_of(int elem, int q, int a, int k)
+{
+    return elem == kT10 ? MassRule<kT10>::grad(q, a, k) : MassRule<kH8>::grad(q, a, k);
+}
 
 // ------------------------------------------------------------------ mesh object
 
@@ -96,12 +153,12 @@ struct ClassRange {
     int elem, law, damped, te;
     int tile_begin, tile_count;
     int nl_cap;          // most distinct nodes of a tile of the class (LDS records to allocate)
-    int nc[3];           // components assembled per round, per operation
+    int nc[6];           // components assembled per round, per kind (kind_slot)
 };
 
 struct GraphEntry {
-    int op;
-    const void *key[9];
+    int kind;
+    const void *key[14];
     hipStream_t stream;
     hipGraphExec_t exec;
     hipEvent_t done;   // recorded after every launch of exec: waited on before exec is destroyed
@@ -132,6 +189,7 @@ struct tlfea_mesh {
     std::vector<GraphEntry> graphs;
     uint64_t stamp = 0;
     bool any_damped = false;
+    bool has_mass = false;     // some block has a density: mass coefficients are on the device
 };
 
 static void free_mesh_memory(tlfea_mesh *m)
@@ -152,8 +210,10 @@ static void free_mesh_memory(tlfea_mesh *m)
     }
 }
 
+// Device copy of a host table, issued on the creation stream (the caller of
+// create_with synchronises the stream before the host tables go away).
 template <class T>
-static tlfea_status upload(tlfea_mesh *m, const std::vector<T> &h, T **d)
+static tlfea_status upload(tlfea_mesh *m, const std::vector<T> &h, T **d, hipStream_t s)
 {
     *d = nullptr;
     if (h.empty()) return TLFEA_OK;
@@ -161,12 +221,22 @@ static tlfea_status upload(tlfea_mesh *m, const std::vector<T> &h, T **d)
     HIP_TRY(hipMalloc(&p, h.size() * sizeof(T)));
     m->allocations.push_back(p);
     m->device_bytes += (int64_t)(h.size() * sizeof(T));
-    HIP_TRY(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
     *d = static_cast<T *>(p);
     return TLFEA_OK;
 }
 
 // ------------------------------------------------------------------ ordering
+
+// Whether a - b is exact in binary64 (Knuth's two-sum error term is zero).
+// Host code is built without value-changing floating-point options.
+static bool difference_is_exact(double a, double b)
+{
+    const volatile double s = a - b;
+    const volatile double bv = s - a;
+    const volatile double av = s - bv;
+    return (a - av) + (-b - bv) == 0.0;
+}
 
 static uint64_t spread21(uint64_t v)
 {
@@ -275,12 +345,16 @@ static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
 // workgroup of te elements has te / 64 waves).  The forward is budgeted for
 // three waves per SIMD and the other operations for their own count, at
 // least two.
-static int64_t lds_budget(int op, int elem, int law, int damped, int te, int64_t lds_dev)
+static int64_t lds_budget(int kind, int elem, int law, int damped, int te, int64_t lds_dev)
 {
-    const int64_t waves_per_cu = op == kOpFwd ? 12 : 4 * std::max(2, waves_per_simd(op, elem, law, damped != 0));
+    const int op = kind_op(kind), mode = kind_mode(kind);
+    const int64_t waves_per_cu =
+        kind == kKFwd ? 12 : (kind == kKMass ? 16 : 4 * std::max(2, waves_per_simd(op, elem, law, damped != 0, mode)));
     const int64_t wgs = std::max<int64_t>(1, waves_per_cu * 64 / te);
     return std::min<int64_t>(lds_dev, 163840 / wgs);
 }
+
+static int kind_record_len(int kind, bool damped) { return record_len(kind_op(kind), damped, kind_mode(kind)); }
 
 static int nl_limit(int elem, int law, int te, int damped, int64_t lds_dev)
 {
@@ -292,29 +366,29 @@ static int nl_limit(int elem, int law, int te, int damped, int64_t lds_dev)
     // slower.  Smaller tiles have proportionally more surface nodes and keep
     // only the LDS limit.
     if (te == 256) nl = std::min<int64_t>(nl, 600);
-    for (int op = kOpFwd; op <= kOpJvp; ++op) {
+    for (int kind : kKinds) {
         const int64_t fixed = 4 + (int64_t)nen * te * 2;
-        const int64_t per_node = 8 * (int64_t)record_len(op, damped != 0) + 8;
-        nl = std::min(nl, (lds_budget(op, elem, law, damped, te, lds_dev) - fixed) / per_node);
+        const int64_t per_node = 8 * (int64_t)kind_record_len(kind, damped != 0) + 8;
+        nl = std::min(nl, (lds_budget(kind, elem, law, damped, te, lds_dev) - fixed) / per_node);
     }
     return (int)nl;
 }
 
 // LDS of one workgroup: the node records (reused for the element slots of
 // nc components), then the tile's assembly tables (see the kernels).
-static size_t lds_bytes(const ClassRange &c, int op, int nc)
+static size_t lds_bytes(const ClassRange &c, int kind, int nc)
 {
-    const size_t records = (size_t)c.nl_cap * record_len(op, c.damped != 0);
+    const size_t records = (size_t)c.nl_cap * kind_record_len(kind, c.damped != 0);
     const size_t slots = (size_t)nc * nen_of(c.elem) * c.te;
     const size_t tables = (size_t)(2 * c.nl_cap + 1) * sizeof(int32_t) + (size_t)nen_of(c.elem) * c.te * sizeof(uint16_t);
     return std::max(records, slots) * sizeof(double) + tables;
 }
 
 // Components assembled per round: as many as fit the operation's budget.
-static int comps_per_round(const ClassRange &c, int op, int64_t lds_dev)
+static int comps_per_round(const ClassRange &c, int kind, int64_t lds_dev)
 {
     for (int nc = 3; nc > 1; --nc)
-        if ((int64_t)lds_bytes(c, op, nc) <= lds_budget(op, c.elem, c.law, c.damped, c.te, lds_dev)) return nc;
+        if ((int64_t)lds_bytes(c, kind, nc) <= lds_budget(kind, c.elem, c.law, c.damped, c.te, lds_dev)) return nc;
     return 1;
 }
 
@@ -587,7 +661,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
     std::vector<std::vector<int64_t>> groups;
     int64_t elem_cursor = 0;
     for (size_t k = 0; k < keys.size(); ++k) {
-        ClassRange cr{keys[k].elem, keys[k].law, keys[k].damped, keys[k].te, (int)hb.tiles.size(), 0, 0, {1, 1, 1}};
+        ClassRange cr{keys[k].elem, keys[k].law, keys[k].damped, keys[k].te, (int)hb.tiles.size(), 0, 0, {1, 1, 1, 1, 1, 1}};
         const int te = keys[k].te, nen = nen_of(keys[k].elem);
         const int nlmax = nl_limit(keys[k].elem, keys[k].law, te, keys[k].damped, lds_dev);
         if (nlmax < nen || (int64_t)nen * te * (int64_t)sizeof(double) > 65536)
@@ -696,7 +770,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
             }
         }
         cr.tile_count = (int)hb.tiles.size() - cr.tile_begin;
-        for (int op = kOpFwd; op <= kOpJvp; ++op) cr.nc[op] = comps_per_round(cr, op, lds_dev);
+        for (int kind : kKinds) cr.nc[kind_slot(kind)] = comps_per_round(cr, kind, lds_dev);
         if (cr.tile_count > 0) hb.classes.push_back(cr);
     }
     if (hb.lnode_slot.size() & 1) hb.lnode_slot.push_back(0);   // whole 32-bit words
@@ -740,6 +814,46 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
 
 // ------------------------------------------------------------------ create / destroy
 
+// A caller-supplied quadrature table (Sec. 6: the rule is tabulated once on
+// the parent element) must be the compiled rule to rounding: the kernels
+// carry the rule's weights and parent gradients as compile-time constants.
+static tlfea_status check_rule(const tlfea_block &B, int b)
+{
+    if (!B.qp_w && !B.dsdxi) {
+        if (B.nq != 0) return fail(TLFEA_E_INVALID, "block %d: nq = %d without a quadrature table", b, B.nq);
+        return TLFEA_OK;
+    }
+    const int nq = nq_of(B.elem), nen = nen_of(B.elem);
+    if (B.nq != nq)
+        return fail(TLFEA_E_UNSUPPORTED, "block %d: a %d-point rule was given; the kernels carry the built-in %d-point "
+                    "rule of this element type", b, B.nq, nq);
+    if (B.qp_w) {
+        double mx = 0;
+        for (int q = 0; q < nq; ++q) mx = std::max(mx, std::fabs(weight_of(B.elem, q)));
+        for (int q = 0; q < nq; ++q) {
+            const double w = weight_of(B.elem, q);
+            if (!(std::fabs(B.qp_w[q] - w) <= 1e-14 * mx))
+                return fail(TLFEA_E_UNSUPPORTED, "block %d: weight of point %d is %.17g, the built-in rule has %.17g; "
+                            "the kernels carry the built-in rule only", b, q, B.qp_w[q], w);
+        }
+    }
+    if (B.dsdxi) {
+        double mx = 0;
+        for (int q = 0; q < nq; ++q)
+            for (int a = 0; a < nen; ++a)
+                for (int k = 0; k < 3; ++k) mx = std::max(mx, std::fabs(grad_of(B.elem, q, a, k)));
+        for (int q = 0; q < nq; ++q)
+            for (int a = 0; a < nen; ++a)
+                for (int k = 0; k < 3; ++k) {
+                    const double g = grad_of(B.elem, q, a, k), d = B.dsdxi[((size_t)q * nen + a) * 3 + k];
+                    if (!(std::fabs(d - g) <= 1e-14 * mx))
+                        return fail(TLFEA_E_UNSUPPORTED, "block %d: parent gradient [%d][%d][%d] is %.17g, the built-in "
+                                    "table has %.17g; the kernels carry the built-in rule only", b, q, a, k, d, g);
+                }
+    }
+    return TLFEA_OK;
+}
+
 static tlfea_status validate_args(int64_t n_nodes, const double *X, int32_t n_blocks, const tlfea_block *blocks,
                                   int32_t flags)
 {
@@ -762,6 +876,12 @@ static tlfea_status validate_args(int64_t n_nodes, const double *X, int32_t n_bl
             return fail(TLFEA_E_INVALID, "block %d: tile_elems must be 0, 64, 128, 192 or 256", b);
         for (int p = 0; p < 5; ++p)
             if (!std::isfinite(B.theta[p])) return fail(TLFEA_E_INVALID, "block %d: theta[%d] not finite", b, p);
+        if (B.reserved != 0) return fail(TLFEA_E_INVALID, "block %d: reserved field must be 0", b);
+        if (!std::isfinite(B.rho) || B.rho < 0) return fail(TLFEA_E_INVALID, "block %d: rho must be finite and >= 0", b);
+        {
+            tlfea_status st = check_rule(B, b);
+            if (st != TLFEA_OK) return st;
+        }
         const int nen = nen_of(B.elem);
         for (int64_t i = 0; i < B.n_elem * nen; ++i)
             if (B.conn[i] < 0 || B.conn[i] >= n_nodes)
@@ -780,7 +900,8 @@ static tlfea_status validate_args(int64_t n_nodes, const double *X, int32_t n_bl
 }
 
 static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_blocks, const tlfea_block *blocks,
-                                int32_t flags, const std::vector<int> &te_of_block, tlfea_mesh **out)
+                                int32_t flags, const std::vector<int> &te_of_block, hipStream_t stream,
+                                tlfea_mesh **out)
 {
     // LDS a workgroup may allocate on this device (the tangent of a damped
     // block, whose node record is the widest, may use all of it)
@@ -824,10 +945,15 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
     m->n_tiles = (int64_t)hb.tiles.size();
     DevMesh &d = m->dm;
     // Reference coordinates per tile node, relative to the tile's node
-    // nearest the centroid of its nodes; the kernels take current positions
-    // relative to the same node.  The differences of nearby coordinates are
-    // exact, and the smaller they are, the less the sums over an element's
-    // nodes (F = N H, J = U G) cancel.
+    // nearest the centroid of its nodes; the kernels that sum positions
+    // directly take current positions relative to the same node.  The
+    // smaller the coordinates, the less the sums over an element's nodes
+    // (F = N H, J = U G) cancel.  A component is taken relative only where
+    // the subtraction is exact for every node of the tile (always so away
+    // from zero, by Sterbenz's lemma): near zero, where it may round, the
+    // coordinates are small already and are kept as they are, so that a
+    // difference of two staged values is always the coordinates' difference
+    // rounded once.
     const int64_t n_tnode = (int64_t)hb.lnode_gid.size();
     std::vector<double> Xt(3 * (size_t)n_tnode);
     for (TileDesc &t : hb.tiles) {
@@ -852,17 +978,22 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
             }
         }
         const int32_t g0 = hb.lnode_gid[t.node_begin + t.ref];
-        for (int l = 0; l < t.n_node; ++l) {
-            const int32_t g = hb.lnode_gid[t.node_begin + l];
-            for (int c = 0; c < 3; ++c)
-                Xt[c * n_tnode + t.node_begin + l] = X[c * n_nodes + g] - X[c * n_nodes + g0];
+        for (int c = 0; c < 3; ++c) {
+            const double o = X[c * n_nodes + g0];
+            bool exact = true;
+            for (int l = 0; l < t.n_node && exact; ++l)
+                exact = difference_is_exact(X[c * n_nodes + hb.lnode_gid[t.node_begin + l]], o);
+            for (int l = 0; l < t.n_node; ++l) {
+                const double xg = X[c * n_nodes + hb.lnode_gid[t.node_begin + l]];
+                Xt[c * n_tnode + t.node_begin + l] = exact ? xg - o : xg;
+            }
         }
     }
     std::vector<double> part_dummy;
 #define UP(vec, ptr)                                                                                       \
     do {                                                                                                   \
         std::remove_const_t<std::remove_pointer_t<decltype(ptr)>> *p_ = nullptr;                           \
-        st = upload(m, vec, &p_);                                                                          \
+        st = upload(m, vec, &p_, stream);                                                                  \
         if (st != TLFEA_OK) { free_mesh_memory(m); delete m; return st; }                                  \
         ptr = p_;                                                                                          \
     } while (0)
@@ -879,6 +1010,46 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
     UP(hb.halo_gid, d.halo_gid);
     UP(hb.halo_ptr, d.halo_ptr);
 #undef UP
+    // Consistent-mass coefficients rho w_q J_p(xi_q) per mass-rule point and
+    // internal element (Sec. 4.1 with the change of variables of Sec. 6),
+    // [nqm][n_elem], J_p from the element's nodes relative to its first node.
+    d.mass_c = nullptr;
+    for (int b = 0; b < n_blocks; ++b) m->has_mass |= blocks[b].rho > 0;
+    if (m->has_mass && m->n_elem > 0) {
+        int nqm = 0;
+        for (int b = 0; b < n_blocks; ++b) nqm = std::max(nqm, nqm_of(blocks[b].elem));
+        std::vector<int64_t> uid0(n_blocks + 1, 0);
+        for (int b = 0; b < n_blocks; ++b) uid0[b + 1] = uid0[b] + blocks[b].n_elem;
+        const int64_t ne = m->n_elem;
+        std::vector<double> mc((size_t)nqm * ne, 0.0);
+        for (const TileDesc &t : hb.tiles) {
+            const tlfea_block &B = blocks[t.block];
+            if (!(B.rho > 0)) continue;
+            const int nen = nen_of(B.elem);
+            for (int i = 0; i < t.n_elem; ++i) {
+                const int64_t ie = t.elem_begin + i;
+                const int32_t *c = B.conn + (hb.elem_uid[ie] - uid0[t.block]) * nen;
+                for (int q = 0; q < nqm_of(B.elem); ++q) {
+                    double J[9] = {0};
+                    for (int a = 1; a < nen; ++a)
+                        for (int r = 0; r < 3; ++r) {
+                            const double u = X[r * n_nodes + c[a]] - X[r * n_nodes + c[0]];
+                            for (int k = 0; k < 3; ++k) J[3 * r + k] += u * mass_grad_of(B.elem, q, a, k);
+                        }
+                    const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                                       J[2] * (J[3] * J[7] - J[4] * J[6]);
+                    mc[(size_t)q * ne + ie] = B.rho * mass_weight_of(B.elem, q) * det;
+                }
+            }
+        }
+        double *p_ = nullptr;
+        st = upload(m, mc, &p_, stream);
+        if (st != TLFEA_OK) { free_mesh_memory(m); delete m; return st; }
+        d.mass_c = p_;
+        // the host table is freed on return: finish the copy now
+        const hipError_t es = hipStreamSynchronize(stream);
+        if (es != hipSuccess) { free_mesh_memory(m); delete m; return fail(TLFEA_E_DEVICE, "%s", hipGetErrorString(es)); }
+    }
     d.n_nodes = n_nodes;
     d.n_elem = m->n_elem;
     d.n_part = hb.n_part;
@@ -896,6 +1067,13 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
         m->allocations.push_back(p);
         m->device_bytes += (int64_t)(sizeof(double) * 6 * hb.n_part);
         d.part = static_cast<double *>(p);
+    }
+    // the host tables above are freed on return: the uploads must be done
+    const hipError_t es = hipStreamSynchronize(stream);
+    if (es != hipSuccess) {
+        free_mesh_memory(m);
+        delete m;
+        return fail(TLFEA_E_DEVICE, "hipStreamSynchronize after the uploads: %s", hipGetErrorString(es));
     }
     *out = m;
     return TLFEA_OK;
@@ -935,24 +1113,28 @@ static tlfea_status timed_launch(tlfea_mesh *m, int kid, hipStream_t s, bool tim
     return TLFEA_OK;
 }
 
-static tlfea_status enqueue(tlfea_mesh *m, int op, const CallArgs &c, hipStream_t s, bool timed)
+// The launches of one call: every tile class, then the shared-node sums.
+// dm is the mesh's device description.
+static tlfea_status enqueue(tlfea_mesh *m, const DevMesh &dm, int kind, const CallArgs &c, hipStream_t s, bool timed)
 {
-    // kernel ids: 0 forward, 1 adjoint, 2 tangent (= op), 3 shared nodes
     for (const ClassRange &cr : m->classes) {
-        const size_t lds = lds_bytes(cr, op, cr.nc[op]);
-        tlfea_status st = timed_launch(m, op, s, timed, "tile kernel", [&] {
-            return launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, s, m->dm, c,
-                                cr.tile_begin, cr.nl_cap, cr.nc[op]);
+        const int nc = cr.nc[kind_slot(kind)];
+        const size_t lds = lds_bytes(cr, kind, nc);
+        tlfea_status st = timed_launch(m, kind, s, timed, "tile kernel", [&] {
+            return launch_tiles(cr.elem, cr.law, cr.damped, cr.te, kind, cr.tile_count, lds, s, dm, c,
+                                cr.tile_begin, cr.nl_cap, nc);
         });
         if (st != TLFEA_OK) return st;
     }
-    double *o1 = (op == kOpVjp) ? c.out1 : nullptr;
-    if (m->dm.n_halo > 0 && (c.out0 || o1))
-        return timed_launch(m, 3, s, timed, "shared-node kernel", [&] { return launch_halo(s, m->dm, c.out0, o1); });
+    double *o1 = (kind == kKVjp) ? c.out1 : nullptr;
+    const double *sub = kind == kKRes ? c.sub : nullptr;
+    if (dm.n_halo > 0 && (c.out0 || o1))
+        return timed_launch(m, 3, s, timed, "shared-node kernel",
+                            [&] { return launch_halo(s, dm, c.out0, o1, sub); });
     return TLFEA_OK;
 }
 
-static tlfea_status run(tlfea_mesh *m, int op, const CallArgs &c, void *stream)
+static tlfea_status run(tlfea_mesh *m, int kind, const CallArgs &c, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = -1;
@@ -964,19 +1146,25 @@ static tlfea_status run(tlfea_mesh *m, int op, const CallArgs &c, void *stream)
     if (s != nullptr) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         HIP_TRY(hipStreamIsCapturing(s, &cs));
-        if (cs != hipStreamCaptureStatusNone) return enqueue(m, op, c, s, false);
+        if (cs != hipStreamCaptureStatusNone) return enqueue(m, m->dm, kind, c, s, false);
     }
     // graphs cannot be captured on the null stream: launch directly there
-    if (!(m->flags & TLFEA_BATCHED) || s == nullptr) return enqueue(m, op, c, s, m->prof);
+    if (!(m->flags & TLFEA_BATCHED) || s == nullptr) return enqueue(m, m->dm, kind, c, s, m->prof);
     // batched: one hipGraph per (op, operand pointers, stream), replayed
-    const void *key[9] = {c.x, c.v, c.theta, c.w, c.dx, c.dv, c.out0, c.out1, c.gtheta};
+    // the time step enters the kernels' arguments: its bits are part of the key
+    uintptr_t hbits = 0;
+    static_assert(sizeof(double) <= sizeof(uintptr_t), "a double fits a pointer-sized key");
+    std::memcpy(&hbits, &c.h, sizeof(double));
+    const void *hkey = reinterpret_cast<const void *>(hbits);
+    const void *key[14] = {c.x, c.v, c.theta, c.w, c.dx, c.dv, c.dtheta, c.qn, c.vn, c.sub, hkey,
+                           c.out0, c.out1, c.gtheta};
     GraphEntry *hit = nullptr;
     for (auto &g : m->graphs)
-        if (g.op == op && g.stream == s && std::memcmp(g.key, key, sizeof key) == 0) hit = &g;
+        if (g.kind == kind && g.stream == s && std::memcmp(g.key, key, sizeof key) == 0) hit = &g;
     if (!hit) {
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        tlfea_status st = enqueue(m, op, c, s, false);
+        tlfea_status st = enqueue(m, m->dm, kind, c, s, false);
         hipError_t ec = hipStreamEndCapture(s, &graph);
         if (st != TLFEA_OK) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -984,7 +1172,7 @@ static tlfea_status run(tlfea_mesh *m, int op, const CallArgs &c, void *stream)
         }
         if (ec != hipSuccess) return fail(TLFEA_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
         GraphEntry ge;
-        ge.op = op;
+        ge.kind = kind;
         std::memcpy(ge.key, key, sizeof key);
         ge.stream = s;
         ge.stamp = ++m->stamp;
@@ -1023,6 +1211,36 @@ static tlfea_status check_mesh(const tlfea_mesh *m)
     return TLFEA_OK;
 }
 
+// A device array of a call: its address range (null arrays are skipped).
+struct Span {
+    const void *p;
+    size_t bytes;
+    const char *name;
+};
+
+static bool overlaps(const Span &a, const Span &b)
+{
+    if (!a.p || !b.p || !a.bytes || !b.bytes) return false;
+    const uintptr_t a0 = (uintptr_t)a.p, b0 = (uintptr_t)b.p;
+    return a0 < b0 + b.bytes && b0 < a0 + a.bytes;
+}
+
+// Outputs are written while tiles still stage inputs, so an output may share
+// no byte with an input or with another output.
+static tlfea_status check_overlap(std::initializer_list<Span> ins, std::initializer_list<Span> outs)
+{
+    for (auto o = outs.begin(); o != outs.end(); ++o) {
+        for (const Span &i : ins)
+            if (overlaps(*o, i)) return fail(TLFEA_E_INVALID, "output %s overlaps input %s", o->name, i.name);
+        for (auto o2 = outs.begin(); o2 != o; ++o2)
+            if (overlaps(*o, *o2)) return fail(TLFEA_E_INVALID, "outputs %s and %s overlap", o2->name, o->name);
+    }
+    return TLFEA_OK;
+}
+
+static size_t nodal_bytes(const tlfea_mesh *m) { return sizeof(double) * 3 * (size_t)m->n_nodes; }
+static size_t param_bytes(const tlfea_mesh *m) { return sizeof(double) * TLFEA_NPAR * (size_t)m->n_elem; }
+
 extern "C" tlfea_status tlfea_internal_force(tlfea_mesh *m, const double *x, const double *v, const double *theta,
                                              double *f, void *stream)
 {
@@ -1030,10 +1248,13 @@ extern "C" tlfea_status tlfea_internal_force(tlfea_mesh *m, const double *x, con
     if (st) return st;
     if (m->n_nodes > 0 && (!x || !f)) return fail(TLFEA_E_INVALID, "x and f are required");
     if (m->any_damped && m->n_elem > 0 && !v) return fail(TLFEA_E_INVALID, "v is required: a block is damped");
+    const size_t nb = nodal_bytes(m), pb = param_bytes(m);
+    st = check_overlap({{x, nb, "x"}, {v, nb, "v"}, {theta, pb, "theta"}}, {{f, nb, "f"}});
+    if (st) return st;
     CallArgs c{};
     c.x = x; c.v = v; c.theta = theta; c.out0 = f;
     if (m->n_nodes == 0) return TLFEA_OK;
-    return run(m, kOpFwd, c, stream);
+    return run(m, kKFwd, c, stream);
 }
 
 extern "C" tlfea_status tlfea_internal_force_vjp(tlfea_mesh *m, const double *x, const double *v, const double *theta,
@@ -1043,23 +1264,289 @@ extern "C" tlfea_status tlfea_internal_force_vjp(tlfea_mesh *m, const double *x,
     if (st) return st;
     if (m->n_nodes > 0 && (!x || !w)) return fail(TLFEA_E_INVALID, "x and w are required");
     if (m->any_damped && m->n_elem > 0 && !v) return fail(TLFEA_E_INVALID, "v is required: a block is damped");
+    const size_t nb = nodal_bytes(m), pb = param_bytes(m);
+    st = check_overlap({{x, nb, "x"}, {v, nb, "v"}, {theta, pb, "theta"}, {w, nb, "w"}},
+                       {{gx, nb, "gx"}, {gv, nb, "gv"}, {gtheta, pb, "gtheta"}});
+    if (st) return st;
     if (m->n_nodes == 0 || (!gx && !gv && !gtheta)) return TLFEA_OK;
     CallArgs c{};
     c.x = x; c.v = v; c.theta = theta; c.w = w; c.out0 = gx; c.out1 = gv; c.gtheta = gtheta;
-    return run(m, kOpVjp, c, stream);
+    return run(m, kKVjp, c, stream);
 }
 
 extern "C" tlfea_status tlfea_tangent_jvp(tlfea_mesh *m, const double *x, const double *v, const double *theta,
-                                          const double *dx, const double *dv, double *df, void *stream)
+                                          const double *dx, const double *dv, const double *dtheta, double *df,
+                                          void *stream)
 {
     tlfea_status st = check_mesh(m);
     if (st) return st;
     if (m->n_nodes > 0 && (!x || !df)) return fail(TLFEA_E_INVALID, "x and df are required");
     if (m->any_damped && m->n_elem > 0 && !v) return fail(TLFEA_E_INVALID, "v is required: a block is damped");
+    const size_t nb = nodal_bytes(m), pb = param_bytes(m);
+    st = check_overlap({{x, nb, "x"}, {v, nb, "v"}, {theta, pb, "theta"}, {dx, nb, "dx"}, {dv, nb, "dv"},
+                        {dtheta, pb, "dtheta"}},
+                       {{df, nb, "df"}});
+    if (st) return st;
     if (m->n_nodes == 0) return TLFEA_OK;
     CallArgs c{};
-    c.x = x; c.v = v; c.theta = theta; c.dx = dx; c.dv = m->any_damped ? dv : nullptr; c.out0 = df;
-    return run(m, kOpJvp, c, stream);
+    c.x = x; c.v = v; c.theta = theta; c.dx = dx; c.dv = m->any_damped ? dv : nullptr; c.dtheta = dtheta;
+    c.out0 = df;
+    return run(m, kKJvp, c, stream);
+}
+
+extern "C" tlfea_status tlfea_mass_action(tlfea_mesh *m, const double *u, double *y, void *stream)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (m->n_nodes > 0 && (!u || !y)) return fail(TLFEA_E_INVALID, "u and y are required");
+    const size_t nb = nodal_bytes(m);
+    st = check_overlap({{u, nb, "u"}}, {{y, nb, "y"}});
+    if (st) return st;
+    if (m->n_nodes == 0) return TLFEA_OK;
+    CallArgs c{};
+    c.x = u; c.out0 = y;
+    return run(m, kKMass, c, stream);
+}
+
+static tlfea_status check_step(double h)
+{
+    if (!std::isfinite(h) || !(h > 0)) return fail(TLFEA_E_INVALID, "time step h = %g must be finite and > 0", h);
+    return TLFEA_OK;
+}
+
+extern "C" tlfea_status tlfea_step_residual(tlfea_mesh *m, const double *q_n, const double *v_n, const double *v,
+                                            double h, const double *theta, const double *f_ext, double *g,
+                                            void *stream)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (m->n_nodes > 0 && (!q_n || !v_n || !v || !g)) return fail(TLFEA_E_INVALID, "q_n, v_n, v and g are required");
+    if ((st = check_step(h))) return st;
+    const size_t nb = nodal_bytes(m), pb = param_bytes(m);
+    st = check_overlap({{q_n, nb, "q_n"}, {v_n, nb, "v_n"}, {v, nb, "v"}, {theta, pb, "theta"}, {f_ext, nb, "f_ext"}},
+                       {{g, nb, "g"}});
+    if (st) return st;
+    if (m->n_nodes == 0) return TLFEA_OK;
+    CallArgs c{};
+    c.v = v; c.qn = q_n; c.vn = v_n; c.h = h; c.theta = theta; c.sub = f_ext; c.out0 = g;
+    return run(m, kKRes, c, stream);
+}
+
+extern "C" tlfea_status tlfea_newton_operator(tlfea_mesh *m, const double *q_n, const double *v, double h,
+                                              const double *theta, const double *dv, double *y, void *stream)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (m->n_nodes > 0 && (!q_n || !v || !dv || !y)) return fail(TLFEA_E_INVALID, "q_n, v, dv and y are required");
+    if ((st = check_step(h))) return st;
+    const size_t nb = nodal_bytes(m), pb = param_bytes(m);
+    st = check_overlap({{q_n, nb, "q_n"}, {v, nb, "v"}, {theta, pb, "theta"}, {dv, nb, "dv"}}, {{y, nb, "y"}});
+    if (st) return st;
+    if (m->n_nodes == 0) return TLFEA_OK;
+    CallArgs c{};
+    c.v = v; c.qn = q_n; c.h = h; c.theta = theta; c.dv = dv; c.out0 = y;
+    return run(m, kKNewt, c, stream);
+}
+
+// ------------------------------------------------------------------ Newton-Krylov step
+
+// Workspace layout of tlfea_newton_step (doubles): the Krylov basis
+// V_0..V_m, then w, x (the increment), b (= -g) and r, each 3 n_nodes long,
+// then the dot-product partial sums.
+static int64_t newton_workspace_doubles(const tlfea_mesh *m, int restart)
+{
+    const int64_t N = 3 * m->n_nodes;
+    return (int64_t)(restart + 5) * N + (int64_t)kDotBlocks * kVecChunk;
+}
+
+extern "C" tlfea_status tlfea_newton_workspace(const tlfea_mesh *m, int32_t restart, int64_t *n_doubles)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (!n_doubles) return fail(TLFEA_E_INVALID, "n_doubles is NULL");
+    if (restart < 1 || restart > 200) return fail(TLFEA_E_INVALID, "restart = %d outside [1, 200]", restart);
+    *n_doubles = newton_workspace_doubles(m, restart);
+    return TLFEA_OK;
+}
+
+namespace {
+
+// The solver's device vector algebra on one stream; every scalar result is
+// summed on the host from fixed per-block partials (bitwise repeatable).
+struct Krylov {
+    tlfea_mesh *m;
+    hipStream_t s;
+    int64_t N;
+    double *partial;
+    std::vector<double> host;
+
+    tlfea_status dots(const double *V, int nvec, const double *w, double *out)
+    {
+        host.resize((size_t)kDotBlocks * kVecChunk);
+        for (int k0 = 0; k0 < nvec; k0 += kVecChunk) {
+            const int nv = std::min(kVecChunk, nvec - k0);
+            hipError_t e = launch_mdot(V + (int64_t)k0 * N, N, nv, w, N, partial, s);
+            if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "dot kernel: %s", hipGetErrorString(e));
+            HIP_TRY(hipMemcpyAsync(host.data(), partial, sizeof(double) * kDotBlocks * nv, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            for (int k = 0; k < nv; ++k) {
+                double t = 0.0;
+                for (int b = 0; b < kDotBlocks; ++b) t += host[(size_t)k * kDotBlocks + b];
+                out[k0 + k] = t;
+            }
+        }
+        return TLFEA_OK;
+    }
+    tlfea_status norm(const double *w, double *out)
+    {
+        double d = 0.0;
+        tlfea_status st = dots(w, 1, w, &d);
+        *out = std::sqrt(d);
+        return st;
+    }
+    // y += sum_k c_k V_k
+    tlfea_status combine(const double *V, int nvec, const double *c, double *y)
+    {
+        for (int k0 = 0; k0 < nvec; k0 += kVecChunk) {
+            const int nv = std::min(kVecChunk, nvec - k0);
+            hipError_t e = launch_maxpy(V + (int64_t)k0 * N, N, nv, c + k0, y, N, s);
+            if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "combination kernel: %s", hipGetErrorString(e));
+        }
+        return TLFEA_OK;
+    }
+    tlfea_status axpby(double a, const double *x, double b, double *y)
+    {
+        hipError_t e = launch_axpby(a, x, b, y, N, s);
+        return e == hipSuccess ? TLFEA_OK : fail(TLFEA_E_DEVICE, "vector kernel: %s", hipGetErrorString(e));
+    }
+};
+
+}  // namespace
+
+// One matrix-free Newton step of the step residual (Sec. 7, without
+// constraints): dv solves (M/h + h K + C) dv = -g(v) approximately by
+// restarted GMRES (classical Gram-Schmidt applied twice, Givens rotations
+// on the host), each operator product one pass of the Newton-operator
+// kernels; v_out = v + dv.
+extern "C" tlfea_status tlfea_newton_step(tlfea_mesh *m, const double *q_n, const double *v_n, const double *v,
+                                          double h, const double *theta, const double *f_ext,
+                                          const tlfea_krylov_opts *opts, double *v_out, double *work,
+                                          int64_t work_len, tlfea_krylov_info *info, void *stream)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (!opts || !info) return fail(TLFEA_E_INVALID, "opts and info are required");
+    if (m->n_nodes > 0 && (!q_n || !v_n || !v || !v_out || !work))
+        return fail(TLFEA_E_INVALID, "q_n, v_n, v, v_out and work are required");
+    if ((st = check_step(h))) return st;
+    const int restart = opts->restart;
+    if (restart < 1 || restart > 200) return fail(TLFEA_E_INVALID, "restart = %d outside [1, 200]", restart);
+    if (opts->max_iters < 1) return fail(TLFEA_E_INVALID, "max_iters must be >= 1");
+    if (!(opts->rtol >= 0) || !std::isfinite(opts->rtol)) return fail(TLFEA_E_INVALID, "rtol must be finite and >= 0");
+    const int64_t need = newton_workspace_doubles(m, restart);
+    if (work_len < need)
+        return fail(TLFEA_E_SHAPE, "workspace of %lld doubles, %lld needed", (long long)work_len, (long long)need);
+    const size_t nb = nodal_bytes(m), pb = param_bytes(m);
+    st = check_overlap({{q_n, nb, "q_n"}, {v_n, nb, "v_n"}, {v, nb, "v"}, {theta, pb, "theta"}, {f_ext, nb, "f_ext"}},
+                       {{v_out, nb, "v_out"}, {work, sizeof(double) * (size_t)work_len, "work"}});
+    if (st) return st;
+    *info = tlfea_krylov_info{};
+    if (m->n_nodes == 0) {
+        info->converged = 1;
+        return TLFEA_OK;
+    }
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != m->device) return fail(TLFEA_E_INVALID, "current device %d differs from the mesh's device %d", dev, m->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t N = 3 * m->n_nodes;
+    double *V = work, *w = work + (int64_t)(restart + 1) * N, *x = w + N, *b = x + N, *r = b + N;
+    Krylov K{m, s, N, r + N, {}};
+    CallArgs rc{};
+    rc.v = v; rc.qn = q_n; rc.vn = v_n; rc.h = h; rc.theta = theta; rc.sub = f_ext; rc.out0 = b;
+    if ((st = enqueue(m, m->dm, kKRes, rc, s, false))) return st;      // b = g(v)
+    if ((st = K.axpby(-1.0, b, 0.0, b))) return st;                   // b = -g
+    if ((st = K.axpby(0.0, b, 0.0, x))) return st;                    // x = 0
+    double gnorm = 0.0;
+    if ((st = K.norm(b, &gnorm))) return st;
+    info->g_norm = gnorm;
+    const double target = opts->rtol * gnorm;
+    auto apply = [&](const double *in, double *out) {   // out = (M/h + hK + C) in
+        CallArgs c{};
+        c.v = v; c.qn = q_n; c.h = h; c.theta = theta; c.dv = in; c.out0 = out;
+        return enqueue(m, m->dm, kKNewt, c, s, false);
+    };
+    double beta = gnorm;
+    const double *r0 = b;            // x = 0: the first residual is b
+    int iters = 0;
+    bool converged = !(beta > target);
+    std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart),
+        hc(restart + 1), hc2(restart + 1);
+    while (!converged && iters < opts->max_iters) {
+        if ((st = K.axpby(1.0 / beta, r0, 0.0, V))) return st;          // V_0 = r / beta
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        for (; j < restart && iters < opts->max_iters; ++j) {
+            double *Vj = V + (int64_t)j * N;
+            if ((st = apply(Vj, w))) return st;
+            // classical Gram-Schmidt, twice
+            if ((st = K.dots(V, j + 1, w, hc.data()))) return st;
+            for (int i = 0; i <= j; ++i) hc2[i] = -hc[i];
+            if ((st = K.combine(V, j + 1, hc2.data(), w))) return st;
+            if ((st = K.dots(V, j + 1, w, hc2.data()))) return st;
+            for (int i = 0; i <= j; ++i) {
+                hc[i] += hc2[i];
+                hc2[i] = -hc2[i];
+            }
+            if ((st = K.combine(V, j + 1, hc2.data(), w))) return st;
+            double hn = 0.0;
+            if ((st = K.norm(w, &hn))) return st;
+            // the new column, rotated by the previous Givens rotations
+            for (int i = 0; i <= j; ++i) H[(size_t)i * restart + j] = hc[i];
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * restart + j], c2 = H[(size_t)(i + 1) * restart + j];
+                H[(size_t)i * restart + j] = cs[i] * a + sn[i] * c2;
+                H[(size_t)(i + 1) * restart + j] = -sn[i] * a + cs[i] * c2;
+            }
+            const double a = H[(size_t)j * restart + j];
+            const double rr = std::hypot(a, hn);
+            cs[j] = rr > 0 ? a / rr : 1.0;
+            sn[j] = rr > 0 ? hn / rr : 0.0;
+            H[(size_t)j * restart + j] = rr;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++iters;
+            const bool breakdown = !(hn > 0);
+            if (!breakdown && j + 1 <= restart)
+                if ((st = K.axpby(1.0 / hn, w, 0.0, V + (int64_t)(j + 1) * N))) return st;
+            if (std::fabs(g[j + 1]) <= target || breakdown) {
+                ++j;
+                break;
+            }
+        }
+        // x += V y, H y = g (upper triangular, j columns)
+        for (int i = j - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int k = i + 1; k < j; ++k) t -= H[(size_t)i * restart + k] * y[k];
+            y[i] = t / H[(size_t)i * restart + i];
+        }
+        if ((st = K.combine(V, j, y.data(), x))) return st;
+        // true residual r = b - A x
+        if ((st = apply(x, w))) return st;
+        if ((st = K.axpby(1.0, b, 0.0, r))) return st;
+        if ((st = K.axpby(-1.0, w, 1.0, r))) return st;
+        if ((st = K.norm(r, &beta))) return st;
+        r0 = r;
+        converged = !(beta > target);
+    }
+    info->iters = iters;
+    info->converged = converged ? 1 : 0;
+    info->res_norm = beta;
+    hipError_t e = launch_add(v, x, v_out, N, s);
+    if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "vector kernel: %s", hipGetErrorString(e));
+    HIP_TRY(hipStreamSynchronize(s));
+    return TLFEA_OK;
 }
 
 extern "C" tlfea_status tlfea_count_inverted(tlfea_mesh *m, const double *x, int64_t *count, void *stream)
@@ -1068,6 +1555,8 @@ extern "C" tlfea_status tlfea_count_inverted(tlfea_mesh *m, const double *x, int
     if (st) return st;
     if (!count) return fail(TLFEA_E_INVALID, "count is NULL");
     if (m->n_nodes > 0 && !x) return fail(TLFEA_E_INVALID, "x is required");
+    st = check_overlap({{x, nodal_bytes(m), "x"}}, {{count, sizeof(int64_t), "count"}});
+    if (st) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));
@@ -1089,7 +1578,7 @@ extern "C" tlfea_status tlfea_count_inverted(tlfea_mesh *m, const double *x, int
 // ------------------------------------------------------------------ autotune
 
 // Time forward + adjoint + tangent per class for one candidate tile size.
-static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vector<double> &t_cls)
+static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, hipStream_t s, std::vector<double> &t_cls)
 {
     const size_t nb = sizeof(double) * 3 * (size_t)m->n_nodes;
     struct Buffers {   // freed on every return
@@ -1102,9 +1591,9 @@ static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vecto
     } buf;
     for (double *&q : buf.p) HIP_TRY(hipMalloc(&q, nb));
     double *x = buf.p[0], *v = buf.p[1], *w = buf.p[2], *o0 = buf.p[3], *o1 = buf.p[4];
-    HIP_TRY(hipMemcpy(x, X_host, nb, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemset(v, 0, nb));
-    HIP_TRY(hipMemset(w, 0, nb));
+    HIP_TRY(hipMemcpyAsync(x, X_host, nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(v, 0, nb, s));
+    HIP_TRY(hipMemsetAsync(w, 0, nb, s));
     EventPair ev;
     HIP_TRY(hipEventCreate(&ev.e0));
     HIP_TRY(hipEventCreate(&ev.e1));
@@ -1112,17 +1601,17 @@ static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vecto
     t_cls.assign(m->classes.size(), 0.0);
     for (size_t k = 0; k < m->classes.size(); ++k) {
         const ClassRange &cr = m->classes[k];
-        for (int op = kOpFwd; op <= kOpJvp; ++op) {
+        for (int op = kKFwd; op <= kKJvp; ++op) {
             CallArgs c{};
-            c.x = x; c.v = v; c.w = w; c.dx = w; c.dv = v; c.out0 = o0; c.out1 = op == kOpVjp ? o1 : nullptr;
-            const size_t lds = lds_bytes(cr, op, cr.nc[op]);
+            c.x = x; c.v = v; c.w = w; c.dx = w; c.dv = v; c.out0 = o0; c.out1 = op == kKVjp ? o1 : nullptr;
+            const size_t lds = lds_bytes(cr, op, cr.nc[kind_slot(op)]);
             float best = 1e30f;
             for (int rep = 0; rep < 4; ++rep) {
-                HIP_TRY(hipEventRecord(e0, nullptr));
-                hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, nullptr, m->dm,
-                                            c, cr.tile_begin, cr.nl_cap, cr.nc[op]);
+                HIP_TRY(hipEventRecord(e0, s));
+                hipError_t e = launch_tiles(cr.elem, cr.law, cr.damped, cr.te, op, cr.tile_count, lds, s, m->dm,
+                                            c, cr.tile_begin, cr.nl_cap, cr.nc[kind_slot(op)]);
                 if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "autotune launch: %s", hipGetErrorString(e));
-                HIP_TRY(hipEventRecord(e1, nullptr));
+                HIP_TRY(hipEventRecord(e1, s));
                 HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0;
                 HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
@@ -1135,15 +1624,16 @@ static tlfea_status time_classes(tlfea_mesh *m, const double *X_host, std::vecto
 }
 
 extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int32_t n_blocks,
-                                          const tlfea_block *blocks, int32_t flags, tlfea_mesh **out)
+                                          const tlfea_block *blocks, int32_t flags, void *stream, tlfea_mesh **out)
 {
     if (!out) return fail(TLFEA_E_INVALID, "out is NULL");
     *out = nullptr;
     tlfea_status st = validate_args(n_nodes, X, n_blocks, blocks, flags);
+    hipStream_t s = static_cast<hipStream_t>(stream);
     if (st) return st;
     std::vector<int> te(n_blocks);
     for (int b = 0; b < n_blocks; ++b) te[b] = blocks[b].tile_elems ? blocks[b].tile_elems : default_te(blocks[b].elem);
-    if (!(flags & TLFEA_AUTOTUNE)) return create_with(n_nodes, X, n_blocks, blocks, flags, te, out);
+    if (!(flags & TLFEA_AUTOTUNE)) return create_with(n_nodes, X, n_blocks, blocks, flags, te, s, out);
     // Autotune: per element type, the tile size with the smallest forward +
     // adjoint + tangent time summed over the classes of that type (one size
     // per type, as tlfea_get_mesh_info reports it); blocks that fix
@@ -1155,10 +1645,10 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
         std::vector<int> tc(n_blocks);
         for (int b = 0; b < n_blocks; ++b) tc[b] = blocks[b].tile_elems ? blocks[b].tile_elems : cand[ci];
         tlfea_mesh *m = nullptr;
-        st = create_with(n_nodes, X, n_blocks, blocks, flags & ~TLFEA_BATCHED, tc, &m);
+        st = create_with(n_nodes, X, n_blocks, blocks, flags & ~TLFEA_BATCHED, tc, s, &m);
         if (st) return st;
         std::vector<double> t;
-        st = time_classes(m, X, t);
+        st = time_classes(m, X, s, t);
         if (st) {
             tlfea_destroy_mesh(m);
             return st;
@@ -1175,7 +1665,7 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
     std::vector<int> best_te = te;
     for (int b = 0; b < n_blocks; ++b)
         if (!blocks[b].tile_elems) best_te[b] = best_c[blocks[b].elem];
-    return create_with(n_nodes, X, n_blocks, blocks, flags, best_te, out);
+    return create_with(n_nodes, X, n_blocks, blocks, flags, best_te, s, out);
 }
 
 extern "C" void tlfea_destroy_mesh(tlfea_mesh *m)
@@ -1275,4 +1765,211 @@ extern "C" tlfea_status tlfea_node_order(const tlfea_mesh *m, int32_t *order)
     for (int64_t g = 0; g < m->n_nodes; ++g)
         if (!seen[g]) order[k++] = (int32_t)g;
     return TLFEA_OK;
+}
+
+// ------------------------------------------------------------------ joints
+
+struct tlfea_joints {
+    int device = 0;
+    DevJoints dj{};
+    std::vector<void *> allocations;
+};
+
+static void free_joints(tlfea_joints *J)
+{
+    for (void *p : J->allocations) (void)hipFree(p);
+    J->allocations.clear();
+}
+
+template <class T>
+static tlfea_status upload_joint(tlfea_joints *J, const std::vector<T> &h, T **d, hipStream_t s)
+{
+    *d = nullptr;
+    if (h.empty()) return TLFEA_OK;
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, h.size() * sizeof(T)));
+    J->allocations.push_back(p);
+    HIP_TRY(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    *d = static_cast<T *>(p);
+    return TLFEA_OK;
+}
+
+extern "C" tlfea_status tlfea_create_joints(int64_t n_nodes, const double *X, int32_t n_joints,
+                                            const tlfea_revolute *joints, void *stream, tlfea_joints **out)
+{
+    if (!out) return fail(TLFEA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_nodes < 0 || n_nodes > INT32_MAX) return fail(TLFEA_E_SHAPE, "n_nodes = %lld out of range", (long long)n_nodes);
+    if (n_joints < 0 || (n_joints > 0 && !joints)) return fail(TLFEA_E_INVALID, "bad joint list");
+    if (n_nodes > 0 && !X) return fail(TLFEA_E_INVALID, "X_ref is NULL");
+    const int64_t nj = n_joints;
+    int nmax = 1;
+    for (int64_t j = 0; j < nj; ++j) {
+        const tlfea_point *pt[5] = {&joints[j].P, &joints[j].Q, &joints[j].R, &joints[j].S, &joints[j].T};
+        for (int p = 0; p < 5; ++p) {
+            if (pt[p]->elem != TLFEA_T10 && pt[p]->elem != TLFEA_H8)
+                return fail(TLFEA_E_INVALID, "joint %lld point %d: unknown element type %d", (long long)j, p, pt[p]->elem);
+            const int nen = nen_of(pt[p]->elem);
+            nmax = std::max(nmax, nen);
+            for (int a = 0; a < nen; ++a)
+                if (pt[p]->nodes[a] < 0 || pt[p]->nodes[a] >= n_nodes)
+                    return fail(TLFEA_E_SHAPE, "joint %lld point %d: node %d outside [0, %lld)", (long long)j, p,
+                                pt[p]->nodes[a], (long long)n_nodes);
+            for (int k = 0; k < 3; ++k)
+                if (!std::isfinite(pt[p]->xi[k]))
+                    return fail(TLFEA_E_INVALID, "joint %lld point %d: parent coordinate not finite", (long long)j, p);
+        }
+    }
+    std::vector<int32_t> ids((size_t)5 * nmax * nj, 0);
+    std::vector<double> sv((size_t)5 * nmax * nj, 0.0), fw((size_t)4 * nj);
+    // per node: (point p, joint j, value) entries
+    std::vector<std::vector<std::pair<int64_t, double>>> by_node;
+    std::vector<int32_t> touched_index(n_nodes, -1);
+    std::vector<int32_t> tnode;
+    for (int64_t j = 0; j < nj; ++j) {
+        const tlfea_point *pt[5] = {&joints[j].P, &joints[j].Q, &joints[j].R, &joints[j].S, &joints[j].T};
+        double r0[5][3];
+        for (int p = 0; p < 5; ++p) {
+            const int nen = nen_of(pt[p]->elem);
+            for (int c = 0; c < 3; ++c) r0[p][c] = 0.0;
+            for (int a = 0; a < nen; ++a) {
+                const double sa = shape_of(pt[p]->elem, a, pt[p]->xi);
+                const int32_t g = pt[p]->nodes[a];
+                const size_t k = ((size_t)p * nmax + a) * nj + j;
+                ids[k] = g;
+                sv[k] = sa;
+                for (int c = 0; c < 3; ++c) r0[p][c] += sa * X[c * n_nodes + g];
+                if (touched_index[g] < 0) {
+                    touched_index[g] = (int32_t)tnode.size();
+                    tnode.push_back(g);
+                    by_node.emplace_back();
+                }
+                by_node[touched_index[g]].push_back({(int64_t)p * nj + j, sa});
+            }
+        }
+        double a0[3], b10[3], b20[3];
+        for (int c = 0; c < 3; ++c) {
+            a0[c] = r0[1][c] - r0[0][c];
+            b10[c] = r0[3][c] - r0[2][c];
+            b20[c] = r0[4][c] - r0[2][c];
+        }
+        const double aa = a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2];
+        const double n1 = aa + b10[0] * b10[0] + b10[1] * b10[1] + b10[2] * b10[2];
+        const double n2 = aa + b20[0] * b20[0] + b20[1] * b20[1] + b20[2] * b20[2];
+        if (!(n1 > 0) || !(n2 > 0))
+            return fail(TLFEA_E_INVALID, "joint %lld: the reference directions vanish (points coincide)", (long long)j);
+        fw[j] = a0[0] * b10[0] + a0[1] * b10[1] + a0[2] * b10[2];
+        fw[nj + j] = a0[0] * b20[0] + a0[1] * b20[1] + a0[2] * b20[2];
+        fw[2 * nj + j] = 1.0 / std::sqrt(n1);
+        fw[3 * nj + j] = 1.0 / std::sqrt(n2);
+    }
+    // entries of each touched node in (joint, point, slot) order; nodes in
+    // ascending order
+    std::vector<int32_t> order(tnode.size());
+    for (size_t t = 0; t < order.size(); ++t) order[t] = (int32_t)t;
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return tnode[x] < tnode[y]; });
+    std::vector<int32_t> tn;
+    std::vector<int64_t> tptr(1, 0), tent;
+    std::vector<double> tval;
+    for (int32_t t : order) {
+        auto &e = by_node[t];
+        std::stable_sort(e.begin(), e.end(), [&](const std::pair<int64_t, double> &x, const std::pair<int64_t, double> &y) {
+            const int64_t jx = x.first % std::max<int64_t>(1, nj), jy = y.first % std::max<int64_t>(1, nj);
+            return jx != jy ? jx < jy : x.first < y.first;
+        });
+        tn.push_back(tnode[t]);
+        for (auto &kv : e) {
+            tent.push_back(kv.first);
+            tval.push_back(kv.second);
+        }
+        tptr.push_back((int64_t)tent.size());
+    }
+    tlfea_joints *J = new (std::nothrow) tlfea_joints();
+    if (!J) return fail(TLFEA_E_NOMEM, "host allocation failed");
+    if (hipGetDevice(&J->device) != hipSuccess) {
+        delete J;
+        return fail(TLFEA_E_DEVICE, "hipGetDevice failed");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevJoints &d = J->dj;
+    d.n_joints = nj;
+    d.n_nodes = n_nodes;
+    d.n_touched = (int64_t)tn.size();
+    d.nmax = nmax;
+    tlfea_status st = TLFEA_OK;
+    {
+        int32_t *pi = nullptr; double *pd = nullptr; int64_t *pl = nullptr;
+        if (!st) { st = upload_joint(J, ids, &pi, s); d.ids = pi; }
+        if (!st) { st = upload_joint(J, sv, &pd, s); d.sv = pd; }
+        if (!st) { st = upload_joint(J, fw, &pd, s); d.fw = pd; }
+        if (!st) { st = upload_joint(J, tn, &pi, s); d.tnode = pi; }
+        if (!st) { st = upload_joint(J, tptr, &pl, s); d.tptr = pl; }
+        if (!st) { st = upload_joint(J, tent, &pl, s); d.tent = pl; }
+        if (!st) { st = upload_joint(J, tval, &pd, s); d.tval = pd; }
+        if (!st && nj > 0) {
+            void *p = nullptr;
+            hipError_t e = hipMalloc(&p, sizeof(double) * 15 * (size_t)nj);
+            if (e != hipSuccess) st = fail(TLFEA_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+            else {
+                J->allocations.push_back(p);
+                d.z = static_cast<double *>(p);
+            }
+        }
+    }
+    if (!st) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(TLFEA_E_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    if (st) {
+        free_joints(J);
+        delete J;
+        return st;
+    }
+    *out = J;
+    return TLFEA_OK;
+}
+
+extern "C" void tlfea_destroy_joints(tlfea_joints *J)
+{
+    if (!J) return;
+    (void)hipDeviceSynchronize();   // no enqueued call may still use the joint set
+    free_joints(J);
+    delete J;
+}
+
+static tlfea_status check_joints(const tlfea_joints *J)
+{
+    if (!J) return fail(TLFEA_E_INVALID, "joint set is NULL");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != J->device) return fail(TLFEA_E_INVALID, "current device %d differs from the joint set's device %d", dev, J->device);
+    return TLFEA_OK;
+}
+
+extern "C" tlfea_status tlfea_joint_values(tlfea_joints *J, const double *q, double *c, void *stream)
+{
+    tlfea_status st = check_joints(J);
+    if (st) return st;
+    if (J->dj.n_joints > 0 && (!q || !c)) return fail(TLFEA_E_INVALID, "q and c are required");
+    st = check_overlap({{q, sizeof(double) * 3 * (size_t)J->dj.n_nodes, "q"}},
+                       {{c, sizeof(double) * 5 * (size_t)J->dj.n_joints, "c"}});
+    if (st) return st;
+    hipError_t e = launch_joints(J->dj, q, nullptr, 0.0, 0.0, c, 0, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TLFEA_OK : fail(TLFEA_E_DEVICE, "joint kernel: %s", hipGetErrorString(e));
+}
+
+extern "C" tlfea_status tlfea_joint_scatter(tlfea_joints *J, const double *q, const double *lambda, double rho,
+                                            double h, double *g, int32_t accumulate, void *stream)
+{
+    tlfea_status st = check_joints(J);
+    if (st) return st;
+    if (J->dj.n_nodes > 0 && (!q || !g)) return fail(TLFEA_E_INVALID, "q and g are required");
+    if (!std::isfinite(rho) || !std::isfinite(h)) return fail(TLFEA_E_INVALID, "rho and h must be finite");
+    const size_t nb = sizeof(double) * 3 * (size_t)J->dj.n_nodes;
+    st = check_overlap({{q, nb, "q"}, {lambda, sizeof(double) * 5 * (size_t)J->dj.n_joints, "lambda"}}, {{g, nb, "g"}});
+    if (st) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_joints(J->dj, q, lambda, rho, h, nullptr, 1, s);
+    if (e == hipSuccess) e = launch_joint_scatter(J->dj, g, accumulate ? 1 : 0, s);
+    return e == hipSuccess ? TLFEA_OK : fail(TLFEA_E_DEVICE, "joint kernel: %s", hipGetErrorString(e));
 }

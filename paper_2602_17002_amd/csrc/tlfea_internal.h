@@ -44,17 +44,30 @@ struct DevMesh {
     const int32_t *halo_gid;      // nodes summed from partials (and nodes no element touches)
     const int32_t *halo_ptr;      // [n_halo + 1]: node h owns partial slots [halo_ptr[h], halo_ptr[h+1])
     double *part;                 // [6][n_part] partial node sums (two fields x three components)
+    const double *mass_c;         // [nqm][n_elem] rho w_q J_p(xi_q) per mass-rule point and internal
+                                  // element (null when no block has a density)
     int64_t n_nodes, n_elem, n_part, n_halo, n_tnode;
 };
 
 // Per-call operands (device pointers; unused ones are null).
 struct CallArgs {
     const double *x, *v, *theta, *w, *dx, *dv;
-    double *out0, *out1;   // f | gx, gv | df
+    const double *dtheta;  // tangent: parameter direction (null: none)
+    const double *qn, *vn; // step residual / Newton operator: q_n, v_n (positions q = q_n + h v)
+    const double *sub;     // subtracted from out0 at every node when non-null (the step residual's f_ext)
+    double h;              // time step of the step map
+    double *out0, *out1;   // f | gx, gv | df | g | y
     double *gtheta;
 };
 
 enum { kOpFwd = 0, kOpVjp = 1, kOpJvp = 2 };
+
+// Variants of the tile kernels: the forward with the step residual's
+// staging and inertia term, the tangent with the Newton operator's.
+enum { kModePlain = 0, kModeStep = 1 };
+// The consistent-mass action has a kernel of its own (operation id 3 of
+// the host's launch tables).
+enum { kOpMass = 3 };
 
 // Waves per SIMD each tile kernel is compiled for (its register budget:
 // 512 / waves registers per lane), shared by the kernels' attributes and the
@@ -66,9 +79,11 @@ enum { kOpFwd = 0, kOpVjp = 1, kOpJvp = 2 };
 // damped adjoint's two sets of accumulators, the other T10 cases), and the
 // damped Mooney-Rivlin adjoint a whole SIMD's registers.  Laws: 0 SVK,
 // 1 Mooney-Rivlin, 2 Neo-Hookean; element 1 is H8.
-constexpr int waves_per_simd(int op, int elem, int law, bool damped)
+constexpr int waves_per_simd(int op, int elem, int law, bool damped, int mode = 0)
 {
-    if (op == kOpFwd) return law == 1 ? 2 : 3;
+    // the step residual stages the adjoint's record length: its LDS budget
+    // is two workgroups per compute unit
+    if (op == kOpFwd) return (law == 1 || mode == 1) ? 2 : 3;
     if (op == kOpVjp && law == 1 && damped) return 1;
     if (damped || law == 1) return 2;
     if (elem == 1) return 3;
@@ -76,16 +91,24 @@ constexpr int waves_per_simd(int op, int elem, int law, bool damped)
 }
 
 // Doubles a node record of an operation holds: X and x, plus w (adjoint) or
-// dx (tangent), plus v when damped, plus dv for the damped tangent.
-constexpr int record_fields_len(int op, bool damped)
+// dx (tangent), plus v when damped, plus dv for the damped tangent.  The
+// step residual (forward, kModeStep) adds u = v - v_n; the Newton operator
+// (tangent, kModeStep) has the tangent's record (dx = h dv).  The mass
+// action stages u only.
+constexpr int record_fields_len(int op, bool damped, int mode = kModePlain)
 {
-    return 6 + (op != kOpFwd ? 3 : 0) + (damped ? 3 : 0) + ((damped && op == kOpJvp) ? 3 : 0);
+    return op == kOpMass ? 3
+                         : 6 + (op != kOpFwd ? 3 : 0) + (damped ? 3 : 0) + ((damped && op == kOpJvp) ? 3 : 0) +
+                               ((op == kOpFwd && mode == kModeStep) ? 3 : 0);
 }
 
 // LDS stride of a node record, rounded up to an odd number of doubles: a
 // wavefront gathers one component of 64 unrelated nodes, and with a stride
 // of 2 x odd dwords the record starts spread over every other bank instead
 // of a quarter or an eighth of them.
-constexpr int record_len(int op, bool damped) { return record_fields_len(op, damped) | 1; }
+constexpr int record_len(int op, bool damped, int mode = kModePlain)
+{
+    return record_fields_len(op, damped, mode) | 1;
+}
 
 }  // namespace tlfea

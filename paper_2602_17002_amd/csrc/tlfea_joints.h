@@ -1,0 +1,21 @@
+// Device layout of a joint set (tlfea_create_joints), shared by the host
+// builder and the joint kernels.
+#pragma once
+#include <stdint.h>
+
+namespace tlfea {
+
+struct DevJoints {
+    int64_t n_joints, n_nodes, n_touched;
+    int nmax;                 // node slots per point (the largest element's node count)
+    const int32_t *ids;       // [5][nmax][n_joints] node of each slot of each point's hosting element
+    const double *sv;         // [5][nmax][n_joints] s_i(xi) of the slot (0 for unused slots)
+    const double *fw;         // [4][n_joints]: f_1, f_2 (a_0.b_10, a_0.b_20), DP1 row weights w_4, w_5
+    double *z;                // [5][3][n_joints] the vector each point receives (scratch)
+    const int32_t *tnode;     // [n_touched] nodes that receive joint forces
+    const int64_t *tptr;      // [n_touched + 1] entry ranges
+    const int64_t *tent;      // [entries] point p and joint j of the entry: p * n_joints + j
+    const double *tval;       // [entries] s_i(xi) of the entry
+};
+
+}  // namespace tlfea

@@ -1,7 +1,13 @@
-// One translation unit per (element type, operation): compiled with
-// -DTLFEA_ELEM=<0|1> -DTLFEA_OP=<0|1|2> so the instantiations build in
-// parallel; the adjoint has two units, -DTLFEA_VJP_GT=<0|1>.  The (T10, forward) unit also holds the shared-node kernel.
+// One translation unit per (element type, operation, variant): compiled
+// with -DTLFEA_ELEM=<0|1> -DTLFEA_OP=<0|1|2> so the instantiations build in
+// parallel; the adjoint has two units, -DTLFEA_VJP_GT=<0|1>, and the forward
+// and the tangent two, -DTLFEA_MODE=<0|1> (the plain operation, or the step
+// residual / Newton operator; the step forward unit also holds the mass
+// action).  The (T10, forward, plain) unit also holds the shared-node
+// kernel.
 #include "tlfea_device.h"
+
+#include <mutex>
 
 #ifndef TLFEA_ELEM
 #error "TLFEA_ELEM must be defined"
@@ -13,38 +19,45 @@
 #ifndef TLFEA_VJP_GT
 #define TLFEA_VJP_GT 0
 #endif
+#ifndef TLFEA_MODE
+#define TLFEA_MODE 0
+#endif
 
-#define TLFEA_CAT2(a, b, c) a##_e##b##_o##c
-#define TLFEA_CAT(a, b, c) TLFEA_CAT2(a, b, c)
-#define TLFEA_CATG2(a, b, c, g) a##_e##b##_o##c##_g##g
-#define TLFEA_CATG(a, b, c, g) TLFEA_CATG2(a, b, c, g)
+#define TLFEA_CAT2(a, b, c, g, md) a##_e##b##_o##c##_g##g##_m##md
+#define TLFEA_CAT(a, b, c, g, md) TLFEA_CAT2(a, b, c, g, md)
 
 namespace tlfea {
 
-#if TLFEA_OP == 1
-// the adjoint units: one per gtheta choice (-DTLFEA_VJP_GT=0|1)
-hipError_t TLFEA_CATG(launch_tiles, TLFEA_ELEM, TLFEA_OP, TLFEA_VJP_GT)(int law, int damped, int te, int n_tiles,
-                                                                        size_t lds, hipStream_t s, const DevMesh &m,
-                                                                        const CallArgs &c, int tile0, int nl, int nc)
-#else
-hipError_t TLFEA_CAT(launch_tiles, TLFEA_ELEM, TLFEA_OP)(int law, int damped, int te, int n_tiles, size_t lds,
-                                                          hipStream_t s, const DevMesh &m, const CallArgs &c,
-                                                          int tile0, int nl, int nc)
-#endif
+hipError_t TLFEA_CAT(launch_tiles, TLFEA_ELEM, TLFEA_OP, TLFEA_VJP_GT, TLFEA_MODE)(
+    int law, int damped, int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
+    int tile0, int nl, int nc)
 {
-    return launch_class<TLFEA_OP, TLFEA_ELEM, TLFEA_VJP_GT>(law, damped, te, n_tiles, lds, s, m, c, tile0, nl, nc);
+    return launch_class<TLFEA_OP, TLFEA_ELEM, TLFEA_VJP_GT, TLFEA_MODE>(law, damped, te, n_tiles, lds, s, m, c,
+                                                                       tile0, nl, nc);
 }
 
-#if TLFEA_OP == 0
-hipError_t TLFEA_CAT(launch_inverted, TLFEA_ELEM, TLFEA_OP)(int te, int n_tiles, size_t lds, hipStream_t s,
-                                                             const DevMesh &m, const CallArgs &c, int tile0,
-                                                             unsigned long long *count)
+#if TLFEA_OP == 0 && TLFEA_MODE == 1
+#define TLFEA_MCAT2(a, b) a##_e##b
+#define TLFEA_MCAT(a, b) TLFEA_MCAT2(a, b)
+hipError_t TLFEA_MCAT(launch_mass, TLFEA_ELEM)(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m,
+                                              const CallArgs &c, int tile0, int nl, int nc)
+{
+    return launch_mass_class<TLFEA_ELEM>(te, n_tiles, lds, s, m, c, tile0, nl, nc);
+}
+#endif
+
+#if TLFEA_OP == 0 && TLFEA_MODE == 0
+#define TLFEA_ICAT2(a, b) a##_e##b##_o0
+#define TLFEA_ICAT(a, b) TLFEA_ICAT2(a, b)
+hipError_t TLFEA_ICAT(launch_inverted, TLFEA_ELEM)(int te, int n_tiles, size_t lds, hipStream_t s,
+                                                  const DevMesh &m, const CallArgs &c, int tile0,
+                                                  unsigned long long *count)
 {
     return launch_inverted_class<TLFEA_ELEM>(te, n_tiles, lds, s, m, c, tile0, count);
 }
 #endif
 
-#if TLFEA_ELEM == 0 && TLFEA_OP == 0
+#if TLFEA_ELEM == 0 && TLFEA_OP == 0 && TLFEA_MODE == 0
 __global__ void k_zero_count(unsigned long long *count) { *count = 0ull; }
 
 hipError_t launch_zero_count(hipStream_t s, unsigned long long *count)
@@ -54,10 +67,11 @@ hipError_t launch_zero_count(hipStream_t s, unsigned long long *count)
 }
 
 // Nodes shared between tiles (and nodes no element touches): sum the node's
-// partial slots, which are contiguous and in tile order.  One lane per node;
-// up to two output fields.  Partials are read eight at a time (every load of
-// a lane in flight together); the sum still runs in tile order.
-__global__ __launch_bounds__(256) void k_halo(DevMesh m, double *out0, double *out1)
+// partial slots, which are contiguous and in tile order, and subtract sub
+// (the step residual's f_ext) when given.  One lane per node; up to two
+// output fields.  Partials are read eight at a time (every load of a lane
+// in flight together); the sum still runs in tile order.
+__global__ __launch_bounds__(256) void k_halo(DevMesh m, double *out0, double *out1, const double *sub)
 {
     const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= m.n_halo) return;
@@ -85,15 +99,18 @@ __global__ __launch_bounds__(256) void k_halo(DevMesh m, double *out0, double *o
                     if (p + u < p1) s[r] += v[r][u];
         }
 #pragma unroll
-        for (int r = 0; r < 3; ++r) out[r * m.n_nodes + g] = s[r];
+        for (int r = 0; r < 3; ++r) {
+            const int64_t o = r * m.n_nodes + g;
+            out[o] = (f == 0 && sub) ? s[r] - sub[o] : s[r];
+        }
     }
 }
 
-hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1)
+hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1, const double *sub)
 {
     if (m.n_halo <= 0) return hipSuccess;
     const dim3 grid((unsigned)((m.n_halo + 255) / 256));
-    k_halo<<<grid, 256, 0, s>>>(m, out0, out1);
+    k_halo<<<grid, 256, 0, s>>>(m, out0, out1, sub);
     return hipGetLastError();
 }
 #endif

@@ -1,0 +1,131 @@
+// Vector kernels of the matrix-free Newton-Krylov step (restarted GMRES on
+// the Newton operator of the step residual): dot products with a fixed
+// reduction order (every result bitwise repeatable), linear combinations,
+// scaling.  Vectors are the solver's flat [3 n_nodes] arrays.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+namespace tlfea {
+
+constexpr int kDotBlocks = 256;   // partial sums per dot product
+constexpr int kVecChunk = 8;      // vectors per launch of the multi-vector kernels
+
+struct Coeffs {
+    double c[kVecChunk];
+};
+
+// partial[k][b] = sum over block b's entries of V_k . w, k < nvec (<= 8),
+// V_k = V + k * ldv.  Block b takes entries b * 256 + t, b * 256 + t +
+// 256 * kDotBlocks, ...; the block's sum is a fixed tree over its threads.
+template <int NV>
+__global__ __launch_bounds__(256) void k_mdot(const double *__restrict__ V, int64_t ldv, const double *__restrict__ w,
+                                              int64_t n, double *__restrict__ partial)
+{
+    __shared__ double red[NV][256];
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)256 * kDotBlocks) {
+        const double wi = w[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[k] += V[k * ldv + i] * wi;
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) partial[k * kDotBlocks + blockIdx.x] = red[k][0];
+}
+
+// y += sum_k c_k V_k, k < NV
+template <int NV>
+__global__ __launch_bounds__(256) void k_maxpy(const double *__restrict__ V, int64_t ldv, Coeffs c,
+                                               double *__restrict__ y, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double t = y[i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t += c.c[k] * V[k * ldv + i];
+    y[i] = t;
+}
+
+// y = a x + b y (b = 0 ignores y's old contents)
+__global__ __launch_bounds__(256) void k_axpby(double a, const double *__restrict__ x, double b, double *__restrict__ y,
+                                               int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
+}
+
+// z = x + y
+__global__ __launch_bounds__(256) void k_add(const double *__restrict__ x, const double *__restrict__ y,
+                                             double *__restrict__ z, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    z[i] = x[i] + y[i];
+}
+
+static dim3 grid_of(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_mdot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *partial,
+                       hipStream_t s)
+{
+    switch (nvec) {
+    case 1: k_mdot<1><<<kDotBlocks, 256, 0, s>>>(V, ldv, w, n, partial); break;
+    case 2: k_mdot<2><<<kDotBlocks, 256, 0, s>>>(V, ldv, w, n, partial); break;
+    case 3: k_mdot<3><<<kDotBlocks, 256, 0, s>>>(V, ldv, w, n, partial); break;
+    case 4: k_mdot<4><<<kDotBlocks, 256, 0, s>>>(V, ldv, w, n, partial); break;
+    case 5: k_mdot<5><<<kDotBlocks, 256, 0, s>>>(V, ldv, w, n, partial); break;
+    case 6: k_mdot<6><<<kDotBlocks, 256, 0, s>>>(V, ldv, w, n, partial); break;
+    case 7: k_mdot<7><<<kDotBlocks, 256, 0, s>>>(V, ldv, w, n, partial); break;
+    case 8: k_mdot<8><<<kDotBlocks, 256, 0, s>>>(V, ldv, w, n, partial); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpy(const double *V, int64_t ldv, int nvec, const double *c, double *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    Coeffs cc{};
+    for (int k = 0; k < nvec && k < kVecChunk; ++k) cc.c[k] = c[k];
+    switch (nvec) {
+    case 1: k_maxpy<1><<<grid_of(n), 256, 0, s>>>(V, ldv, cc, y, n); break;
+    case 2: k_maxpy<2><<<grid_of(n), 256, 0, s>>>(V, ldv, cc, y, n); break;
+    case 3: k_maxpy<3><<<grid_of(n), 256, 0, s>>>(V, ldv, cc, y, n); break;
+    case 4: k_maxpy<4><<<grid_of(n), 256, 0, s>>>(V, ldv, cc, y, n); break;
+    case 5: k_maxpy<5><<<grid_of(n), 256, 0, s>>>(V, ldv, cc, y, n); break;
+    case 6: k_maxpy<6><<<grid_of(n), 256, 0, s>>>(V, ldv, cc, y, n); break;
+    case 7: k_maxpy<7><<<grid_of(n), 256, 0, s>>>(V, ldv, cc, y, n); break;
+    case 8: k_maxpy<8><<<grid_of(n), 256, 0, s>>>(V, ldv, cc, y, n); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_axpby<<<grid_of(n), 256, 0, s>>>(a, x, b, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(const double *x, const double *y, double *z, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_add<<<grid_of(n), 256, 0, s>>>(x, y, z, n);
+    return hipGetLastError();
+}
+
+}  // namespace tlfea

@@ -14,17 +14,32 @@
 namespace tlfea {
 // The builder's translation unit refers to the kernel launchers; nothing here
 // launches anything.
-hipError_t launch_halo(hipStream_t, const DevMesh &, double *, double *) { return hipErrorInvalidValue; }
+hipError_t launch_halo(hipStream_t, const DevMesh &, double *, double *, const double *) { return hipErrorInvalidValue; }
 hipError_t launch_inverted_e0_o0(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int,
                                  unsigned long long *) { return hipErrorInvalidValue; }
 hipError_t launch_inverted_e1_o0(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int,
                                  unsigned long long *) { return hipErrorInvalidValue; }
 hipError_t launch_zero_count(hipStream_t, unsigned long long *) { return hipErrorInvalidValue; }
-#define TLFEA_STUB(e, o)                                                                                          \
-    hipError_t launch_tiles_e##e##_o##o(int, int, int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, \
-                                        int, int, int) { return hipErrorInvalidValue; }
-TLFEA_STUB(0, 0) TLFEA_STUB(0, 1_g0) TLFEA_STUB(0, 1_g1) TLFEA_STUB(0, 2)
-TLFEA_STUB(1, 0) TLFEA_STUB(1, 1_g0) TLFEA_STUB(1, 1_g1) TLFEA_STUB(1, 2)
+hipError_t launch_mass_e0(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int, int)
+{ return hipErrorInvalidValue; }
+hipError_t launch_mass_e1(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int, int)
+{ return hipErrorInvalidValue; }
+hipError_t launch_mdot(const double *, int64_t, int, const double *, int64_t, double *, hipStream_t)
+{ return hipErrorInvalidValue; }
+hipError_t launch_maxpy(const double *, int64_t, int, const double *, double *, int64_t, hipStream_t)
+{ return hipErrorInvalidValue; }
+hipError_t launch_axpby(double, const double *, double, double *, int64_t, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_add(const double *, const double *, double *, int64_t, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_joints(const DevJoints &, const double *, const double *, double, double, double *, int, hipStream_t)
+{ return hipErrorInvalidValue; }
+hipError_t launch_joint_scatter(const DevJoints &, double *, int, hipStream_t) { return hipErrorInvalidValue; }
+#define TLFEA_STUB(e, o, g, md)                                                                                  \
+    hipError_t launch_tiles_e##e##_o##o##_g##g##_m##md(int, int, int, int, size_t, hipStream_t, const DevMesh &, \
+                                                       const CallArgs &, int, int, int) { return hipErrorInvalidValue; }
+TLFEA_STUB(0, 0, 0, 0) TLFEA_STUB(0, 0, 0, 1) TLFEA_STUB(0, 1, 0, 0) TLFEA_STUB(0, 1, 1, 0)
+TLFEA_STUB(0, 2, 0, 0) TLFEA_STUB(0, 2, 0, 1)
+TLFEA_STUB(1, 0, 0, 0) TLFEA_STUB(1, 0, 0, 1) TLFEA_STUB(1, 1, 0, 0) TLFEA_STUB(1, 1, 1, 0)
+TLFEA_STUB(1, 2, 0, 0) TLFEA_STUB(1, 2, 0, 1)
 #undef TLFEA_STUB
 }  // namespace tlfea
 

@@ -1,0 +1,104 @@
+"""GPU parity of the revolute joints (Sec. 2.2, App. B.1) through the C ABI:
+row-normalised values and the transpose scatter h C^T (lambda + rho c)
+against the oracle, on T10 and H8 hosting elements, with joints sharing
+nodes, in overwrite and accumulate modes, bitwise repeatable, and on many
+joints over the 1,020,000-element box."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from _util import TOL, rel, to_dev, to_host
+from test_gpu_parity import say
+from test_oracle_constraints import two_bodies
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_point(rng, X, conn, elem):
+    e = int(rng.integers(conn.shape[0]))
+    if elem == synth.T10:
+        b = rng.dirichlet(np.ones(4))
+        xi = b[1:]
+    else:
+        xi = rng.uniform(-1, 1, 3)
+    return (elem, conn[e].tolist(), xi.tolist())
+
+
+def _random_joints(rng, X, cb, eb, cc, ec, n):
+    out = []
+    for _ in range(n):
+        out.append(dict(P=_random_point(rng, X, cb, eb), Q=_random_point(rng, X, cb, eb),
+                        R=_random_point(rng, X, cc, ec), S=_random_point(rng, X, cc, ec),
+                        T=_random_point(rng, X, cc, ec)))
+    return out
+
+
+@pytest.mark.parametrize("n_joints", [1, 37, 300])
+def test_joint_values_and_scatter_match_oracle(n_joints):
+    from paper_2602_17002_amd.joints import Joints
+    X, (cb, cc), hinge, rng = two_bodies(seed=n_joints)
+    joints = [hinge] + _random_joints(rng, X, cb, synth.T10, cc, synth.H8, n_joints - 1)
+    q = X + rng.normal(0, 5e-4, X.shape)
+    lam = rng.normal(0, 1, (n_joints, 5))
+    say("joints", n_joints)
+    J = Joints(X, joints)
+    c = to_host(J.values(to_dev(q)))
+    cr = O.revolute_values(X, q, joints)
+    assert rel(c, cr) <= TOL
+    rho, h = 3e4, 1e-3
+    g = to_host(J.scatter(to_dev(q), to_dev(lam), rho, h))
+    gr = O.revolute_scatter(X, q, joints, lam, rho, h)
+    assert rel(g, gr) <= TOL
+    # nodes of no joint are exactly 0 in overwrite mode
+    touched = np.unique(np.concatenate([np.asarray(jt[k][1]) for jt in joints for k in "PQRST"]))
+    mask = np.ones(X.shape[1], bool); mask[touched] = False
+    assert np.all(g[:, mask] == 0)
+    # accumulate onto a given vector; no lambda
+    base = rng.normal(0, 1, X.shape)
+    out = to_dev(base)
+    J.scatter(to_dev(q), None, rho, h, out=out, accumulate=True)
+    assert rel(to_host(out) - base, O.revolute_scatter(X, q, joints, None, rho, h)) <= 1e-11
+    # repeatable bit for bit
+    g2 = to_host(J.scatter(to_dev(q), to_dev(lam), rho, h))
+    assert np.array_equal(g, g2)
+
+
+def test_joint_scatter_full_size_box():
+    """4,000 joints with points in random elements of the 1,020,000-element
+    T10 box, many sharing nodes; every node's scattered force against the
+    oracle evaluated joint by joint."""
+    from paper_2602_17002_amd.joints import Joints
+    p = synth.config_c2()
+    rng = np.random.default_rng(95)
+    conn = p.blocks[0].conn
+    joints = []
+    for _ in range(4000):
+        jt = {k: _random_point(rng, p.X, conn, synth.T10) for k in "PQRST"}
+        joints.append(jt)
+    # a cluster of joints on one element, so that nodes collect many entries
+    for _ in range(50):
+        jt = {k: (synth.T10, conn[123].tolist(), rng.dirichlet(np.ones(4))[1:].tolist()) for k in "PQRST"}
+        joints.append(jt)
+    say("joints full size", len(joints))
+    J = Joints(p.X, joints)
+    lam = rng.normal(0, 1, (len(joints), 5))
+    g = to_host(J.scatter(to_dev(p.x), to_dev(lam), 1e4, 1e-3))
+    gr = O.revolute_scatter_local(p.X, p.x, joints, lam, 1e4, 1e-3)
+    assert rel(g, gr) <= TOL
+    assert rel(to_host(J.values(to_dev(p.x))), O.revolute_values(p.X, p.x, joints)) <= TOL
+
+
+def test_joint_creation_rejects_bad_input():
+    from paper_2602_17002_amd import TlfeaError
+    from paper_2602_17002_amd.joints import Joints
+    X, _, hinge, _ = two_bodies()
+    bad = dict(hinge)
+    bad["Q"] = (synth.T10, [X.shape[1] + 5] + list(hinge["Q"][1][1:]), hinge["Q"][2])
+    with pytest.raises(TlfeaError) as ei:
+        Joints(X, [bad])
+    assert ei.value.status == -2
+    same = dict(hinge); same["Q"] = hinge["P"]; same["S"] = hinge["R"]
+    with pytest.raises(TlfeaError) as ei:
+        Joints(X, [same])
+    assert ei.value.status == -1

@@ -1,0 +1,209 @@
+"""GPU parity of the inertia and step operations through the C ABI: the
+consistent-mass action (Sec. 4.1), the backward-Euler step residual without
+constraints and its Newton operator (Sec. 7), against the oracle on the
+same inputs (norm-wise relative error <= 1e-12 per output array)."""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from _util import TOL, rel, to_dev, to_host
+from test_gpu_parity import CASES, _id, make_problem, mesh_of, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _step_inputs(p, seed, h):
+    rng = np.random.default_rng(seed)
+    q_n = p.x
+    v_n = rng.normal(0, 0.3, p.X.shape)
+    v = v_n + rng.normal(0, 0.3, p.X.shape)
+    f_ext = rng.normal(0, 10.0, p.X.shape)
+    dv = rng.normal(0, 1.0, p.X.shape)
+    return q_n, v_n, v, f_ext, dv
+
+
+def _with_rho(p, rho):
+    q = copy.copy(p)
+    q.blocks = [copy.copy(b) for b in p.blocks]
+    for b in q.blocks:
+        b.rho = rho
+    return q
+
+
+@pytest.mark.parametrize("tile", [64, 256])
+@pytest.mark.parametrize("elem", [synth.T10, synth.H8], ids=["T10", "H8"])
+def test_mass_action_matches_oracle(elem, tile):
+    p = _with_rho(make_problem(elem, "NH", False, n=(9, 6, 4), seed=80, curved=True), 1350.0)
+    say("mass action", p.name, tile)
+    m = mesh_of(p, tile=tile)
+    u = np.random.default_rng(81).normal(0, 1, p.X.shape)
+    y = to_host(m.mass_action(to_dev(u)))
+    assert rel(y, O.mass_action(p.X, p.blocks, u)) <= TOL
+
+
+def test_mass_action_multiblock_densities():
+    """Two bodies of different density in one mesh, and a third of zero
+    density (no inertia: its nodes get exactly 0)."""
+    p = synth.config_multibody(3, 300, 2000, seed=82)
+    for b, rho in zip(p.blocks, (800.0, 7800.0, 0.0)):
+        b.rho = rho
+    say("mass multiblock", p.n_elem)
+    m = mesh_of(p)
+    u = np.random.default_rng(83).normal(0, 1, p.X.shape)
+    y = to_host(m.mass_action(to_dev(u)))
+    assert rel(y, O.mass_action(p.X, p.blocks, u)) <= TOL
+    n0, n1 = p.body_nodes[2]
+    assert np.all(y[:, n0:n1] == 0)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_step_residual_and_newton_operator_match_oracle(case):
+    elem, law, damped = case
+    p = _with_rho(make_problem(elem, law, damped, per_elem=True, curved=True, seed=84), 1100.0)
+    h = 1e-4
+    q_n, v_n, v, f_ext, dv = _step_inputs(p, 85, h)
+    say("step", p.name)
+    m = mesh_of(p, tile=128)
+    th = to_dev(p.theta_all())
+    g = to_host(m.step_residual(to_dev(q_n), to_dev(v_n), to_dev(v), h, th, to_dev(f_ext)))
+    ref = O.step_residual(p.X, p.blocks, q_n, v_n, v, h, f_ext)
+    assert rel(g, ref) <= TOL, rel(g, ref)
+    # without f_ext
+    g0 = to_host(m.step_residual(to_dev(q_n), to_dev(v_n), to_dev(v), h, th))
+    assert rel(g0, O.step_residual(p.X, p.blocks, q_n, v_n, v, h)) <= TOL
+    y = to_host(m.newton_operator(to_dev(q_n), to_dev(v), h, th, to_dev(dv)))
+    refy = O.newton_operator(p.X, p.blocks, q_n, v, h, dv)
+    assert rel(y, refy) <= TOL, rel(y, refy)
+
+
+def test_step_operations_reduce_to_their_terms():
+    """Zero density: the residual is f_int(q_n + h v, v) - f_ext, and the
+    Newton operator is the tangent with dx = h dv (both through the GPU's
+    own calls); zero parameters: the residual is the inertia term alone."""
+    p = make_problem(synth.T10, "NH", True, per_elem=True, seed=86)
+    h = 2e-4
+    q_n, v_n, v, f_ext, dv = _step_inputs(p, 87, h)
+    m = mesh_of(p)
+    th = to_dev(p.theta_all())
+    q = O.step_positions(h, v, q_n)
+    g = to_host(m.step_residual(to_dev(q_n), to_dev(v_n), to_dev(v), h, th, to_dev(f_ext)))
+    f = to_host(m.internal_force(to_dev(q), to_dev(v), th))
+    assert np.array_equal(g, f - f_ext)
+    y = to_host(m.newton_operator(to_dev(q_n), to_dev(v), h, th, to_dev(dv)))
+    k = to_host(m.jvp(to_dev(q), to_dev(v), to_dev(h * dv), to_dev(dv), th))
+    assert np.array_equal(y, k)
+    pr = _with_rho(p, 2000.0)
+    mr = mesh_of(pr)
+    g = to_host(mr.step_residual(to_dev(q_n), to_dev(v_n), to_dev(v), h, th * 0.0))
+    mu = to_host(mr.mass_action(to_dev(v - v_n)))
+    assert rel(g, mu / h) <= 1e-15
+
+
+@pytest.mark.parametrize("flags", ["plain", "batched"])
+def test_step_operations_multibody(flags):
+    from paper_2602_17002_amd import BATCHED
+    p = synth.config_multibody(10, 300, 4000, seed=88, directions=True)
+    for i, b in enumerate(p.blocks):
+        b.rho = 500.0 + 300.0 * i
+    h = 5e-4
+    q_n, v_n, v, f_ext, dv = _step_inputs(p, 89, h)
+    say("step multibody", flags, p.n_elem)
+    m = mesh_of(p, flags=BATCHED if flags == "batched" else 0)
+    import torch
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        args = [to_dev(a) for a in (q_n, v_n, v, f_ext, dv)]
+        for rep in range(2):   # a batched mesh captures, then replays
+            g = to_host(m.step_residual(args[0], args[1], args[2], h, None, args[3]))
+            y = to_host(m.newton_operator(args[0], args[2], h, None, args[4]))
+            assert rel(g, O.step_residual(p.X, p.blocks, q_n, v_n, v, h, f_ext)) <= TOL
+            assert rel(y, O.newton_operator(p.X, p.blocks, q_n, v, h, dv)) <= TOL
+
+
+def test_step_full_size_c2_whole_outputs():
+    """The 1,020,000-element Neo-Hookean + Kelvin-Voigt box with a density:
+    mass action, step residual and Newton operator over the whole mesh
+    against the oracle (split over CPU workers)."""
+    import _oracle_pool
+    p = synth.config_c2()
+    m0 = mesh_of(p)
+    p = p.renumbered(m0.node_order())
+    m0.close()
+    p = _with_rho(p, 1100.0)
+    h = 1e-4
+    q_n, v_n, v, f_ext, dv = _step_inputs(p, 90, h)
+    say("C2 step operations", p.n_elem)
+    m = mesh_of(p)
+    d = {k: to_dev(a) for k, a in dict(qn=q_n, vn=v_n, v=v, dv=dv).items()}
+    mu = to_host(m.mass_action(d["dv"]))
+    g = to_host(m.step_residual(d["qn"], d["vn"], d["v"], h))
+    y = to_host(m.newton_operator(d["qn"], d["v"], h, None, d["dv"]))
+    ref = _oracle_pool.run(p.X, p.blocks, dict(u=dv, qn=q_n, vn=v_n, v=v, dv=dv), ["mass", "res", "newt"], h=h)
+    for name, a, b in (("M dv", mu, ref["mu"]), ("g", g, ref["g"]), ("newton", y, ref["y"])):
+        e = rel(a, b)
+        say("C2", name, "rel", e)
+        assert e <= TOL, (name, e)
+
+
+@pytest.mark.parametrize("damped", [False, True], ids=["el", "KV"])
+def test_newton_step_solves_the_newton_system(damped):
+    """The GMRES step against the oracle's direct solve of the assembled
+    (M/h + hK + C) dv = -g: the oracle's residual of the GPU increment is
+    below the requested tolerance, and the increment's error is within the
+    perturbation bound cond(A) ||r|| / ||g||; two calls agree bitwise."""
+    p = _with_rho(make_problem(synth.T10, "NH", damped, n=(6, 4, 3), per_elem=True, curved=True, seed=91), 1100.0)
+    h = 1e-4
+    q_n, v_n, v, f_ext, dv = _step_inputs(p, 92, h)
+    say("newton step", p.name)
+    m = mesh_of(p)
+    th = p.theta_all()
+    args = [to_dev(a) for a in (q_n, v_n, v)]
+    vo, info = m.newton_step(*args, h, to_dev(th), to_dev(f_ext), restart=40, max_iters=800, rtol=1e-10)
+    vo2, info2 = m.newton_step(*args, h, to_dev(th), to_dev(f_ext), restart=40, max_iters=800, rtol=1e-10)
+    assert info["converged"] == 1 and info == info2
+    vo, vo2 = to_host(vo), to_host(vo2)
+    assert np.array_equal(vo, vo2)
+    v_ex, dv_ex, g = O.newton_step(p.X, p.blocks, q_n, v_n, v, h, f_ext)
+    assert abs(info["g_norm"] - np.linalg.norm(g)) <= 1e-12 * np.linalg.norm(g)
+    dv_gpu = vo - v
+    r = O.newton_operator(p.X, p.blocks, q_n, v, h, dv_gpu) + g
+    rr = np.linalg.norm(r) / np.linalg.norm(g)
+    A = O.newton_matrix(p.X, p.blocks, q_n, v, h).toarray()
+    kappa = np.linalg.cond(A)
+    err = np.linalg.norm(dv_gpu - dv_ex) / np.linalg.norm(dv_ex)
+    say("newton step iters", info["iters"], "oracle residual", rr, "cond", kappa, "error", err)
+    # the GPU's own estimate and the oracle's residual of the GPU increment
+    assert info["res_norm"] <= 1e-10 * info["g_norm"]
+    assert rr <= 1e-9
+    assert err <= 2 * kappa * rr + 1e-14
+
+
+def test_newton_steps_converge_quadratically_on_gpu():
+    """Repeated GPU Newton-Krylov steps from the predictor v = v_n: the
+    step residual (from the GPU's own call, checked against the oracle at
+    every iterate) falls quadratically, as the oracle's exact steps do."""
+    p = _with_rho(make_problem(synth.T10, "NH", True, n=(6, 4, 3), per_elem=True, seed=93), 1100.0)
+    h = 1e-4
+    q_n, v_n, _, f_ext, _ = _step_inputs(p, 94, h)
+    m = mesh_of(p)
+    th = to_dev(p.theta_all())
+    qd, vnd, fd = to_dev(q_n), to_dev(v_n), to_dev(f_ext)
+    vk = vnd.clone()
+    norms = []
+    for it in range(4):
+        g = to_host(m.step_residual(qd, vnd, vk, h, th, fd))
+        vh = to_host(vk)
+        ref = O.step_residual(p.X, p.blocks, q_n, v_n, vh, h, f_ext)
+        # near the solution g is a small difference of large terms: the
+        # bound scales with the terms (inertia, internal force, f_ext)
+        q = O.step_positions(h, vh, q_n)
+        scale = (np.abs(O.mass_action(p.X, p.blocks, vh - v_n)).max() / h
+                 + np.abs(O.internal_force(p.X, p.blocks, q, vh)).max() + np.abs(f_ext).max())
+        assert np.abs(g - ref).max() <= TOL * scale
+        norms.append(np.abs(ref).max())
+        vk, info = m.newton_step(qd, vnd, vk, h, th, fd, restart=60, max_iters=1200, rtol=1e-11)
+    say("GPU Newton residuals", norms)
+    assert norms[1] <= 0.1 * norms[0] and norms[2] <= 0.01 * norms[1] and norms[3] <= 1e-4 * norms[2]
