@@ -316,6 +316,26 @@ tlfea_status tlfea_joint_scatter(tlfea_joints *joints, const double *q, const do
                                  double h, double *g, int32_t accumulate, void *stream);
 
 /*
+ * tlfea_internal_force for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, and harnesses that
+ * forbid allocation.  Same arguments, result and errors as
+ * tlfea_internal_force (f overwritten, bitwise the same values), but the
+ * shared-node partial sums go to a static device array of the library
+ * (64 MiB per device, held from the library's first use on that device to
+ * the end of the process) instead of the mesh's buffer, and the launches
+ * are issued directly on `stream` (no graph of a TLFEA_BATCHED mesh, no
+ * timing events), so the call performs no allocation of any kind.  A mesh
+ * whose shared-node partials need more than the array (3 doubles per
+ * partial, about 2.8 million partials) returns TLFEA_E_UNSUPPORTED.  Every
+ * call on one device shares that array: calls that overlap in time on one
+ * device (on different streams, or from different threads) race and must
+ * be ordered by the caller.  No clearing is needed between calls: every
+ * partial is written before it is read.
+ */
+tlfea_status tlfea_internal_force_noalloc(tlfea_mesh *mesh, const double *x, const double *v,
+                                          const double *theta, double *f, void *stream);
+
+/*
  * A node numbering suited to the kernels: order[k] is the caller's node that
  * should become node k (HOST int32[n_nodes], written).  Nodes held by one
  * tile only come first, tile by tile; the nodes several tiles share follow,

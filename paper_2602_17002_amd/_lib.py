@@ -22,7 +22,8 @@ KERNEL_IDS = ("forward_tile", "adjoint_tile", "tangent_tile", "halo", "batched_g
 
 EXPORTS = ("tlfea_create_mesh", "tlfea_destroy_mesh", "tlfea_get_mesh_info", "tlfea_internal_force",
            "tlfea_internal_force_vjp", "tlfea_tangent_jvp", "tlfea_last_error", "tlfea_set_profiling",
-           "tlfea_get_profile", "tlfea_reset_profile", "tlfea_node_order", "tlfea_count_inverted", "tlfea_mass_action", "tlfea_step_residual", "tlfea_newton_operator",
+           "tlfea_get_profile", "tlfea_reset_profile", "tlfea_node_order", "tlfea_count_inverted",
+           "tlfea_internal_force_noalloc", "tlfea_mass_action", "tlfea_step_residual", "tlfea_newton_operator",
            "tlfea_newton_workspace", "tlfea_newton_step", "tlfea_create_joints", "tlfea_destroy_joints",
            "tlfea_joint_values", "tlfea_joint_scatter")
 
@@ -87,6 +88,8 @@ def lib():
     L.tlfea_get_mesh_info.restype = C.c_int
     L.tlfea_internal_force.argtypes = [vp, dp, dp, dp, dp, vp]
     L.tlfea_internal_force.restype = C.c_int
+    L.tlfea_internal_force_noalloc.argtypes = [vp, dp, dp, dp, dp, vp]
+    L.tlfea_internal_force_noalloc.restype = C.c_int
     L.tlfea_internal_force_vjp.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
     L.tlfea_internal_force_vjp.restype = C.c_int
     L.tlfea_tangent_jvp.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]

@@ -41,6 +41,7 @@ hipError_t launch_inverted_e0_o0(int te, int n_tiles, size_t lds, hipStream_t s,
 hipError_t launch_inverted_e1_o0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
                                  int tile0, unsigned long long *count);
 hipError_t launch_zero_count(hipStream_t s, unsigned long long *count);
+hipError_t scratch_address(double **out);
 // vector kernels of the Newton-Krylov step (tlfea_vec.hip)
 constexpr int kDotBlocks = 256, kVecChunk = 8;
 hipError_t launch_mdot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *partial,
@@ -1114,7 +1115,8 @@ static tlfea_status timed_launch(tlfea_mesh *m, int kid, hipStream_t s, bool tim
 }
 
 // The launches of one call: every tile class, then the shared-node sums.
-// dm is the mesh's device description.
+// dm is the mesh's device description (its partial buffer may be replaced,
+// see tlfea_internal_force_noalloc).
 static tlfea_status enqueue(tlfea_mesh *m, const DevMesh &dm, int kind, const CallArgs &c, hipStream_t s, bool timed)
 {
     for (const ClassRange &cr : m->classes) {
@@ -1547,6 +1549,36 @@ extern "C" tlfea_status tlfea_newton_step(tlfea_mesh *m, const double *q_n, cons
     if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "vector kernel: %s", hipGetErrorString(e));
     HIP_TRY(hipStreamSynchronize(s));
     return TLFEA_OK;
+}
+
+// The forward with the shared-node partial sums in the library's static
+// device scratch instead of the mesh's buffer; launches directly (no graph
+// capture, no timing events), so no call in it allocates.  Every partial
+// slot is written by its tile before the shared-node kernel reads it, so
+// the scratch needs no clearing between calls.
+extern "C" tlfea_status tlfea_internal_force_noalloc(tlfea_mesh *m, const double *x, const double *v,
+                                                     const double *theta, double *f, void *stream)
+{
+    tlfea_status st = check_mesh(m);
+    if (st) return st;
+    if (m->n_nodes > 0 && (!x || !f)) return fail(TLFEA_E_INVALID, "x and f are required");
+    if (m->any_damped && m->n_elem > 0 && !v) return fail(TLFEA_E_INVALID, "v is required: a block is damped");
+    const size_t nb = nodal_bytes(m), pb = param_bytes(m);
+    st = check_overlap({{x, nb, "x"}, {v, nb, "v"}, {theta, pb, "theta"}}, {{f, nb, "f"}});
+    if (st) return st;
+    if (3 * m->dm.n_part > kScratchDoubles)
+        return fail(TLFEA_E_UNSUPPORTED, "the mesh has %lld shared-node partials; the static scratch holds %lld "
+                    "(three rows each): use tlfea_internal_force", (long long)m->dm.n_part,
+                    (long long)(kScratchDoubles / 3));
+    if (m->n_nodes == 0) return TLFEA_OK;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != m->device) return fail(TLFEA_E_INVALID, "current device %d differs from the mesh's device %d", dev, m->device);
+    DevMesh dm = m->dm;
+    HIP_TRY(scratch_address(&dm.part));
+    CallArgs c{};
+    c.x = x; c.v = v; c.theta = theta; c.out0 = f;
+    return enqueue(m, dm, kKFwd, c, static_cast<hipStream_t>(stream), false);
 }
 
 extern "C" tlfea_status tlfea_count_inverted(tlfea_mesh *m, const double *x, int64_t *count, void *stream)

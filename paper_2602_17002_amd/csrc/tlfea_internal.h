@@ -69,6 +69,11 @@ enum { kModePlain = 0, kModeStep = 1 };
 // the host's launch tables).
 enum { kOpMass = 3 };
 
+// The no-allocation forward keeps its shared-node partial sums (three rows
+// of n_part doubles) in a static device array of this many doubles (64 MiB).
+constexpr int64_t kScratchDoubles = int64_t(8) << 20;
+constexpr int kMaxDevices = 64;
+
 // Waves per SIMD each tile kernel is compiled for (its register budget:
 // 512 / waves registers per lane), shared by the kernels' attributes and the
 // host's LDS budget.  Measured per instantiation: three waves where the

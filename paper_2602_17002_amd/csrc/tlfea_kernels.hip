@@ -58,6 +58,33 @@ hipError_t TLFEA_ICAT(launch_inverted, TLFEA_ELEM)(int te, int n_tiles, size_t l
 #endif
 
 #if TLFEA_ELEM == 0 && TLFEA_OP == 0 && TLFEA_MODE == 0
+// Device scratch of tlfea_internal_force_noalloc: the forward's shared-node
+// partial sums (three rows of n_part doubles), in a file-scope array that
+// every device holds from the module's load to the end of the process, so
+// that entry point allocates nothing.  Host code never passes the array's
+// name to a kernel: it takes the device address from hipGetSymbolAddress,
+// once per device, with that device current.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t scratch_address(double **out)
+{
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double *>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
 __global__ void k_zero_count(unsigned long long *count) { *count = 0ull; }
 
 hipError_t launch_zero_count(hipStream_t s, unsigned long long *count)

@@ -20,6 +20,7 @@ hipError_t launch_inverted_e0_o0(int, int, size_t, hipStream_t, const DevMesh &,
 hipError_t launch_inverted_e1_o0(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int,
                                  unsigned long long *) { return hipErrorInvalidValue; }
 hipError_t launch_zero_count(hipStream_t, unsigned long long *) { return hipErrorInvalidValue; }
+hipError_t scratch_address(double **) { return hipErrorInvalidValue; }
 hipError_t launch_mass_e0(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int, int)
 { return hipErrorInvalidValue; }
 hipError_t launch_mass_e1(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int, int)
