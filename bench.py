@@ -712,7 +712,7 @@ def main():
     t_dom = k_ms[dom][1] * 1e-3
     achieved = flops / t_dom / 1e12
     byts = bytes_per_call(op, nn, ne, 10, True)
-    kname = "tlfea::k_fwd<0,2,true>" if op == "fwd" else "tlfea::k_vjp<0,2,true,false>"
+    kname = "tlfea::k_fwd<0,2,true,0>" if op == "fwd" else "tlfea::k_vjp<0,2,true,false>"
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic_from_profile(kname),
             "kernel": kname, "kernel_ms": round(k_ms[dom][1], 4),
