@@ -16,6 +16,7 @@ HIP events on the stream.
 
 The line also carries: the 204,000-element per-element-parameter body's
 adjoint with parameter gradients and tangent (skip with --no-c4); the
+131,072-element Q27 body's forward, adjoint and tangent (skip with --no-q27); the
 multibody comparison (skip with --no-batched): 512 bodies of 200-50,000
 elements (mixed T10 / H8, SVK / Neo-Hookean), forward internal force of
 every body, timed as one batched mesh (one hipGraph replay) against one plain
@@ -62,6 +63,27 @@ SVK, MR, NH = 0, 1, 2
 # at the point (T10 5-point rule: 12, 21, 20, 20, 19; H8 2x2x2 Gauss: 24).
 # A gathered field costs 6 nz (G = sum_a s_a g_a^T), the scatter 6 nz.
 NZ = {T10: [12, 21, 20, 20, 19], H8: [24] * 8}
+Q27 = 2
+
+
+def _q27_nz():
+    """Non-zero parent-gradient entries at each 3x3x3 Gauss point of Q27: at
+    a coordinate 0 only L_1 (value) and L_0', L_2' (derivative) are non-zero
+    along that direction, elsewhere all three of each."""
+    out = []
+    for q in range(27):
+        zero = [(q // 3 ** d) % 3 == 1 for d in range(3)]
+        nz = 0
+        for k in range(3):
+            c = 1
+            for d in range(3):
+                c *= (2 if d == k else 1) if zero[d] else 3
+            nz += c
+        out.append(nz)
+    return out
+
+
+NZ[Q27] = _q27_nz()
 GEOM = 33            # cofactor of J (27) + det (5) + reciprocal (1)
 TOREF = 54           # A = (G cof(J)^T) / det J for one field
 TOPAR = 54           # Q = w_q P cof(J)
@@ -110,11 +132,15 @@ def flops_per_element(op, elem, law, damped, gtheta=False):
 # consistent-mass action per element: at each point of the mass rule
 # (T10 15 points, H8 8) the interpolation of u (3 x nen FMA), the scaling
 # (3 mul + 1) and the scatter (3 x nen FMA)
-MASS_QP = {T10: 15, H8: 8}
-NEN = {T10: 10, H8: 8}
+MASS_QP = {T10: 15, H8: 8, Q27: 27}
+NEN = {T10: 10, H8: 8, Q27: 27}
 
 
 def mass_flops_per_element(elem):
+    if elem == Q27:
+        # non-zero shape values at each point: 3 per direction, 1 at a coordinate 0
+        nzs = [int(np.prod([1 if (q // 3 ** d) % 3 == 1 else 3 for d in range(3)])) for q in range(27)]
+        return sum(2 * 3 * z + 4 + 2 * 3 * z for z in nzs)
     return MASS_QP[elem] * (2 * 3 * NEN[elem] + 4 + 2 * 3 * NEN[elem])
 
 
@@ -266,6 +292,47 @@ def c4_ops(steps, warmup):
             out[name] = {"ms": round(med, 4), "quad_pts_per_s": p.n_qp / (med * 1e-3),
                          "flops_per_element": fpe,
                          "frac_fp64_peak": round(fpe * p.n_elem / (med * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+    return out
+
+
+def q27_ops(steps, warmup):
+    """The 131,072-element Q27 body (64 x 64 x 32 cells, 3,538,944 points),
+    Neo-Hookean + Kelvin-Voigt: the forward, the adjoint (gx, gv) and the
+    tangent, each timed alone (median of per-call event pairs), the step
+    (forward + adjoint) as in the headline line."""
+    import torch
+
+    import synth
+    from paper_2602_17002_amd import Mesh
+    p = synth.config_q27()
+    dev = torch.device("cuda", 0)
+    m = Mesh.from_problem(p)
+    p = p.renumbered(m.node_order())
+    m.close()
+    m = Mesh.from_problem(p)
+    s = torch.cuda.Stream(device=dev)
+    info = m.info()
+    out = {"workload": "Q27: 131,072 Q27 box 64x64x32 cells, 3x3x3 Gauss, Neo-Hookean + Kelvin-Voigt",
+           "quad_points": p.n_qp, "tile_elems": info["tile_elems_q27"], "tiles": info["n_tiles"]}
+    with torch.cuda.stream(s):
+        x, v, w, dx, dv = (torch.from_numpy(a).to(dev) for a in (p.x, p.v, p.w, p.dx, p.dv))
+        f, gx, gv, df = (torch.empty_like(x) for _ in range(4))
+        ops = (("forward", lambda: m.internal_force(x, v, out=f), flops_per_element("fwd", Q27, NH, True)),
+               ("adjoint_gx_gv", lambda: m.vjp(x, v, w, want_theta=False, out=(gx, gv, None)),
+                flops_per_element("vjp", Q27, NH, True)),
+               ("tangent", lambda: m.jvp(x, v, dx, dv, out=df), flops_per_element("jvp", Q27, NH, True)))
+        for name, fn, fpe in ops:
+            med, mean, _ = timed(fn, steps, warmup, s)
+            out[name] = {"ms": round(med, 4), "quad_pts_per_s": p.n_qp / (med * 1e-3),
+                         "flops_per_element": fpe,
+                         "frac_fp64_peak": round(fpe * p.n_elem / (med * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+
+        def step():
+            m.internal_force(x, v, out=f)
+            m.vjp(x, v, w, want_theta=False, out=(gx, gv, None))
+
+        med, _, _ = timed(step, steps, warmup, s)
+        out["step_fwd_adjoint"] = {"ms": round(med, 4), "quad_pts_per_s": p.n_qp / (med * 1e-3)}
     return out
 
 
@@ -607,6 +674,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-body batched vs plain comparison")
     ap.add_argument("--no-c5", action="store_true", help="skip the 256-body forward + adjoint + tangent graph")
     ap.add_argument("--no-c4", action="store_true", help="skip the 204,000-element per-element-parameter adjoint and tangent")
+    ap.add_argument("--no-q27", action="store_true", help="skip the 131,072-element Q27 forward, adjoint and tangent")
     ap.add_argument("--no-step", action="store_true", help="skip the mass, step residual, Newton operator and Newton-Krylov step")
     ap.add_argument("--no-joints", action="store_true", help="skip the revolute-joint values and scatter")
     ap.add_argument("--keep-node-order", action="store_true",
@@ -737,6 +805,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_c4:
         out["c4"] = c4_ops(args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    if not args.no_q27:
+        out["q27"] = q27_ops(args.steps, args.warmup)
         torch.cuda.empty_cache()
     if not args.no_step:
         out["step"] = step_ops(args.steps, args.warmup)

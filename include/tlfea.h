@@ -71,7 +71,7 @@ typedef enum {
     TLFEA_E_UNSUPPORTED = -6     /* valid request the library does not handle */
 } tlfea_status;
 
-enum { TLFEA_T10 = 0, TLFEA_H8 = 1 };          /* element types            */
+enum { TLFEA_T10 = 0, TLFEA_H8 = 1, TLFEA_Q27 = 2 };   /* element types   */
 enum { TLFEA_SVK = 0, TLFEA_MR = 1, TLFEA_NH = 2 };  /* constitutive laws  */
 enum { TLFEA_NPAR = 5 };                         /* parameter rows          */
 
@@ -89,8 +89,11 @@ enum {
  * tetrahedron): corners at parent (0,0,0), (1,0,0), (0,1,0), (0,0,1), then
  * mid-edge nodes 1-2, 2-3, 1-3, 1-4, 2-4, 3-4.  H8 (not in the paper) is the
  * trilinear hexahedron on [-1,1]^3 with nodes in the paper's Q27 convention
- * (lexicographic, i fastest).  Quadrature of the internal force: T10 5-point
- * degree-3 rule, H8 2x2x2 Gauss.
+ * (lexicographic, i fastest).  Q27 is the paper's 27-node triquadratic
+ * hexahedron (App. A): node i + 3 j + 9 k at parent (i - 1, j - 1, k - 1),
+ * shape functions products of the 1-D quadratic Lagrange polynomials.
+ * Quadrature of the internal force: T10 5-point degree-3 rule, H8 2x2x2
+ * Gauss, Q27 3x3x3 Gauss (points in node order: q = p0 + 3 p1 + 9 p2).
  *
  * The quadrature rule is tabulated once on the parent element and reused
  * for every element (Sec. 6, approximation of integrals): nq points with
@@ -104,13 +107,14 @@ enum {
  * only.
  */
 typedef struct {
-    int32_t elem;            /* TLFEA_T10 or TLFEA_H8                          */
+    int32_t elem;            /* TLFEA_T10, TLFEA_H8 or TLFEA_Q27               */
     int32_t law;             /* TLFEA_SVK, TLFEA_MR or TLFEA_NH                */
     int64_t n_elem;          /* elements in this block, >= 0                   */
     const int32_t *conn;     /* HOST [n_elem][nen], 0-based global node ids    */
     double theta[5];         /* default parameter rows (used when theta==NULL) */
     int32_t damped;          /* nonzero: Kelvin-Voigt branch active            */
-    int32_t tile_elems;      /* elements per tile: 0 = default, else 64/128/192/256 */
+    int32_t tile_elems;      /* elements per tile: 0 = default, else 64/128/192/256
+                                (Q27: 64 or 128)                               */
     int32_t nq;              /* points of qp_w / dsdxi (0 when both are NULL)  */
     int32_t reserved;        /* must be 0                                      */
     const double *qp_w;      /* HOST [nq] quadrature weights, or NULL          */
@@ -124,6 +128,7 @@ typedef struct {
     int64_t n_tiles, n_halo_nodes, n_partials;
     int32_t n_blocks, flags;
     int32_t tile_elems_t10, tile_elems_h8;   /* chosen (autotuned) tile sizes  */
+    int32_t tile_elems_q27, reserved;
     int64_t device_bytes;                    /* device memory the mesh holds   */
 } tlfea_mesh_info;
 
@@ -197,8 +202,8 @@ tlfea_status tlfea_tangent_jvp(tlfea_mesh *mesh, const double *x, const double *
  * with rho = 0 contribute nothing).  The mass integrals use a rule exact for
  * straight-sided elements (the paper tabulates one rule per element on the
  * parent domain, Sec. 6, and does not name the mass rule): T10 the 15-point
- * degree-5 rule, H8 2x2x2 Gauss; rho w_q J_p(xi_q) is formed once at mesh
- * creation.  u, y: DEVICE [3][n_nodes]; y overwritten.
+ * degree-5 rule, H8 2x2x2 Gauss, Q27 its 3x3x3 Gauss rule; rho w_q J_p(xi_q)
+ * is formed once at mesh creation.  u, y: DEVICE [3][n_nodes]; y overwritten.
  */
 tlfea_status tlfea_mass_action(tlfea_mesh *mesh, const double *u, double *y, void *stream);
 
@@ -281,7 +286,7 @@ tlfea_status tlfea_newton_step(tlfea_mesh *mesh, const double *q_n, const double
 typedef struct tlfea_joints tlfea_joints;   /* opaque, immutable */
 
 typedef struct {
-    int32_t elem;           /* TLFEA_T10 or TLFEA_H8: the hosting element's type  */
+    int32_t elem;           /* TLFEA_T10, TLFEA_H8 or TLFEA_Q27: the host element */
     int32_t nodes[27];      /* its node ids, element node order (first nen used)  */
     double xi[3];           /* parent coordinates of the material point           */
 } tlfea_point;

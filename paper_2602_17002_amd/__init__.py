@@ -5,10 +5,10 @@ The computation lives in the HIP library ``libtlfea.so`` behind the C ABI of
 ``Mesh`` or ``TLInternalForce`` loads the library and fails loudly if it has
 not been built.
 """
-from ._lib import AUTOTUNE, BATCHED, H8, KEEP_ORDER, MR, NH, PLAIN, SVK, T10, TlfeaError  # noqa: F401
+from ._lib import AUTOTUNE, BATCHED, H8, KEEP_ORDER, MR, NH, PLAIN, Q27, SVK, T10, TlfeaError  # noqa: F401
 
 __all__ = ["Mesh", "TLInternalForce", "internal_force", "TlfeaError",
-           "T10", "H8", "SVK", "MR", "NH", "PLAIN", "BATCHED", "AUTOTUNE", "KEEP_ORDER"]
+           "T10", "H8", "Q27", "SVK", "MR", "NH", "PLAIN", "BATCHED", "AUTOTUNE", "KEEP_ORDER"]
 
 
 def __getattr__(name):

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtlfea.so")
 TLFEA_OK = 0
 STATUS_NAMES = {0: "TLFEA_OK", -1: "TLFEA_E_INVALID", -2: "TLFEA_E_SHAPE", -3: "TLFEA_E_REF_JACOBIAN",
                 -4: "TLFEA_E_NOMEM", -5: "TLFEA_E_DEVICE", -6: "TLFEA_E_UNSUPPORTED"}
-T10, H8 = 0, 1
+T10, H8, Q27 = 0, 1, 2
 SVK, MR, NH = 0, 1, 2
 PLAIN, BATCHED, AUTOTUNE, KEEP_ORDER = 0, 1, 2, 4
 KERNEL_IDS = ("forward_tile", "adjoint_tile", "tangent_tile", "halo", "batched_graph", "residual_tile",
@@ -42,6 +42,7 @@ class MeshInfo(C.Structure):
                 ("n_tiles", C.c_int64), ("n_halo_nodes", C.c_int64), ("n_partials", C.c_int64),
                 ("n_blocks", C.c_int32), ("flags", C.c_int32),
                 ("tile_elems_t10", C.c_int32), ("tile_elems_h8", C.c_int32),
+                ("tile_elems_q27", C.c_int32), ("reserved", C.c_int32),
                 ("device_bytes", C.c_int64)]
 
 

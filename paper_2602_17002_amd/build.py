@@ -17,7 +17,7 @@ HOST = os.path.join(CSRC, "tlfea_host.cpp")
 # of tlfea_kernels.hip; the adjoint is compiled once without and once with
 # the parameter gradients, the forward and the tangent once plain and once
 # as their step variant (step residual, Newton operator)
-UNITS = [(e, o, g, md) for e in (0, 1) for o in (0, 1, 2) for g in ((0, 1) if o == 1 else (0,))
+UNITS = [(e, o, g, md) for e in (0, 1, 2) for o in (0, 1, 2) for g in ((0, 1) if o == 1 else (0,))
          for md in ((0, 1) if o != 1 else (0,))]
 # extra compiler flags per unit (element, operation, gradients): the adjoint
 # holds two sets of nodal accumulators, and the scheduler that minimises

@@ -50,6 +50,73 @@ __device__ __forceinline__ void point_loop(Fn &&fn)
     }
 }
 
+// The quadrature points of an element type: T10 and H8 as point_loop
+// (each point a compile-time instance, passed as integral_constant); Q27 as
+// a plain loop whose index is the same in every lane of the wavefront, so
+// that the per-point 1-D tables below are read into scalar registers.
+template <int ELEM, class Fn>
+__device__ __forceinline__ void for_points(Fn &&fn)
+{
+    if constexpr (ELEM == kQ27) {
+#pragma nounroll
+        for (int q = 0; q < ElemDef<kQ27>::nq; ++q) fn(q);
+    } else {
+        point_loop<ElemDef<ELEM>::nq>(fn);
+    }
+}
+
+// Q27 per-point tables: for parent coordinate index p (the Gauss point
+// -sqrt(3/5), 0, +sqrt(3/5)) the 1-D values L_0..L_2 and derivatives
+// L_0'..L_2'; and the 27 point weights in point order.
+struct Q27Tab {
+    double v[3][6];
+    double w[27];
+};
+static __constant__ Q27Tab kQ27Tab = {
+    {{ElemDef<kQ27>::lag1(0, -ElemDef<kQ27>::g), ElemDef<kQ27>::lag1(1, -ElemDef<kQ27>::g),
+      ElemDef<kQ27>::lag1(2, -ElemDef<kQ27>::g), ElemDef<kQ27>::dlag1(0, -ElemDef<kQ27>::g),
+      ElemDef<kQ27>::dlag1(1, -ElemDef<kQ27>::g), ElemDef<kQ27>::dlag1(2, -ElemDef<kQ27>::g)},
+     {ElemDef<kQ27>::lag1(0, 0.0), ElemDef<kQ27>::lag1(1, 0.0), ElemDef<kQ27>::lag1(2, 0.0),
+      ElemDef<kQ27>::dlag1(0, 0.0), ElemDef<kQ27>::dlag1(1, 0.0), ElemDef<kQ27>::dlag1(2, 0.0)},
+     {ElemDef<kQ27>::lag1(0, ElemDef<kQ27>::g), ElemDef<kQ27>::lag1(1, ElemDef<kQ27>::g),
+      ElemDef<kQ27>::lag1(2, ElemDef<kQ27>::g), ElemDef<kQ27>::dlag1(0, ElemDef<kQ27>::g),
+      ElemDef<kQ27>::dlag1(1, ElemDef<kQ27>::g), ElemDef<kQ27>::dlag1(2, ElemDef<kQ27>::g)}},
+    {ElemDef<kQ27>::weight(0), ElemDef<kQ27>::weight(1), ElemDef<kQ27>::weight(2), ElemDef<kQ27>::weight(3),
+     ElemDef<kQ27>::weight(4), ElemDef<kQ27>::weight(5), ElemDef<kQ27>::weight(6), ElemDef<kQ27>::weight(7),
+     ElemDef<kQ27>::weight(8), ElemDef<kQ27>::weight(9), ElemDef<kQ27>::weight(10), ElemDef<kQ27>::weight(11),
+     ElemDef<kQ27>::weight(12), ElemDef<kQ27>::weight(13), ElemDef<kQ27>::weight(14), ElemDef<kQ27>::weight(15),
+     ElemDef<kQ27>::weight(16), ElemDef<kQ27>::weight(17), ElemDef<kQ27>::weight(18), ElemDef<kQ27>::weight(19),
+     ElemDef<kQ27>::weight(20), ElemDef<kQ27>::weight(21), ElemDef<kQ27>::weight(22), ElemDef<kQ27>::weight(23),
+     ElemDef<kQ27>::weight(24), ElemDef<kQ27>::weight(25), ElemDef<kQ27>::weight(26)}};
+
+// 1-D values of the three directions at Q27 point q (L: values, D:
+// derivatives; [direction][node index along it]).
+struct Q27Pt {
+    double L[3][3], D[3][3];
+};
+__device__ __forceinline__ Q27Pt q27_point(int q)
+{
+    Q27Pt t;
+    const int p[3] = {q % 3, (q / 3) % 3, q / 9};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            t.L[d][i] = kQ27Tab.v[p[d]][i];
+            t.D[d][i] = kQ27Tab.v[p[d]][3 + i];
+        }
+    return t;
+}
+
+// Weight of point q of an element type (q an integral_constant, or an int
+// for Q27).
+template <int ELEM, class QT>
+__device__ __forceinline__ double weight_at(QT q)
+{
+    if constexpr (ELEM == kQ27) return kQ27Tab.w[(int)q];
+    else return ElemDef<ELEM>::weight(QT::value);
+}
+
 typedef double m3[3][3];
 
 __device__ __forceinline__ void mm(const m3 &A, const m3 &B, m3 &R)   // R = A B
@@ -131,9 +198,17 @@ __device__ __forceinline__ void qp_fence() { __asm__ __volatile__("" ::: "memory
 // the nodes' coordinate difference rounded once: the current positions of
 // these kernels are staged raw, and the reference ones relative to the tile's
 // reference node only where that subtraction was exact.
-template <int ELEM, int Q, int NEN, bool REL = false>
-__device__ __forceinline__ void grad_field(const double *__restrict__ s, const int (&na)[NEN], m3 &G)
+template <int ELEM, int NEN, bool REL, class QT>
+__device__ __forceinline__ void grad_field_q27(QT q, const double *__restrict__ s, const int (&na)[NEN], m3 &G);
+
+template <int ELEM, int NEN, bool REL = false, class QT>
+__device__ __forceinline__ void grad_field(QT qc, const double *__restrict__ s, const int (&na)[NEN], m3 &G)
 {
+    if constexpr (ELEM == kQ27) {
+        grad_field_q27<ELEM, NEN, REL>(qc, s, na, G);
+        return;
+    } else {
+    constexpr int Q = QT::value;
     using E = ElemDef<ELEM>;
     qp_fence();
 #pragma unroll
@@ -161,13 +236,108 @@ __device__ __forceinline__ void grad_field(const double *__restrict__ s, const i
             });
         }
     });
+    }
+}
+
+// Q27 gradient at point q by sum factorisation: with (p0, p1, p2) the
+// point's Gauss indices, G_c = sum_ijk s_ijk,c (L'_i L_j L_k, L_i L'_j L_k,
+// L_i L_j L'_k), contracted over i, then j, then k (90 multiply-adds per
+// component instead of the 81 of a stored 27 x 3 table, with 18 table
+// values per point instead of 81).  REL as for grad_field.
+template <int ELEM, int NEN, bool REL, class QT>
+__device__ __forceinline__ void grad_field_q27(QT q, const double *__restrict__ s, const int (&na)[NEN], m3 &G)
+{
+    static_assert(NEN == 27, "Q27");
+    qp_fence();
+    const Q27Pt t = q27_point((int)q);
+    double o[3] = {0.0, 0.0, 0.0};
+    if constexpr (REL) {
+        o[0] = s[na[0]];
+        o[1] = s[na[0] + 1];
+        o[2] = s[na[0] + 2];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) G[c][0] = G[c][1] = G[c][2] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        // one plane of nodes (27 values) in flight at a time
+        qp_fence();
+        double ck[3] = {0.0, 0.0, 0.0}, dk[3] = {0.0, 0.0, 0.0}, ek[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double a[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int n = i + 3 * j + 9 * k;
+                if (REL && n == 0) continue;   // s_0 - s_0
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double v = s[na[n] + c] - o[c];
+                    a[c] += t.D[0][i] * v;
+                    b[c] += t.L[0][i] * v;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ck[c] += t.L[1][j] * a[c];
+                dk[c] += t.D[1][j] * b[c];
+                ek[c] += t.L[1][j] * b[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            G[c][0] += t.L[2][k] * ck[c];
+            G[c][1] += t.L[2][k] * dk[c];
+            G[c][2] += t.D[2][k] * ek[c];
+        }
+    }
+}
+
+// Q27 transpose of grad_field_q27: out[ijk][c] += sum_m Qm[c][m] g_m with
+// g = (L'_i L_j L_k, L_i L'_j L_k, L_i L_j L'_k), factored from k inwards.
+template <int NEN, int SKIP_LAST, class QT>
+__device__ __forceinline__ void scatter_grad_q27(QT q, const m3 &Qm, double (&out)[NEN][3])
+{
+    static_assert(NEN == 27, "Q27");
+    const Q27Pt t = q27_point((int)q);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double t0[3], t1[3], t2[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            t0[c] = t.L[2][k] * Qm[c][0];
+            t1[c] = t.L[2][k] * Qm[c][1];
+            t2[c] = t.D[2][k] * Qm[c][2];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double u[3], w[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                u[c] = t.L[1][j] * t0[c];                       // multiplies L'_i
+                w[c] = t.D[1][j] * t1[c] + t.L[1][j] * t2[c];   // multiplies L_i
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int n = i + 3 * j + 9 * k;
+                if (SKIP_LAST && n == NEN - 1) continue;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) out[n][c] += t.D[0][i] * u[c] + t.L[0][i] * w[c];
+            }
+        }
+    }
 }
 
 // out[a][r] += sum_k Q[r][k] (ds_a/dxi at point Q)_k   (i.e. c P h_a with Q = c P J^{-T}),
 // for every node but the last when SKIP_LAST (see finish_last_node)
-template <int ELEM, int QP, int NEN, int SKIP_LAST = 0>
-__device__ __forceinline__ void scatter_grad(const m3 &Qm, double (&out)[NEN][3])
+template <int ELEM, int NEN, int SKIP_LAST = 0, class QT>
+__device__ __forceinline__ void scatter_grad(QT qc, const m3 &Qm, double (&out)[NEN][3])
 {
+    if constexpr (ELEM == kQ27) {
+        scatter_grad_q27<NEN, SKIP_LAST>(qc, Qm, out);
+        return;
+    } else {
+    constexpr int QP = QT::value;
     using E = ElemDef<ELEM>;
     static_for<NEN - SKIP_LAST>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
@@ -181,6 +351,7 @@ __device__ __forceinline__ void scatter_grad(const m3 &Qm, double (&out)[NEN][3]
             }
         });
     });
+    }
 }
 
 // The parent gradients of an element sum to zero at every point (the shape
@@ -204,12 +375,12 @@ __device__ __forceinline__ void finish_last_node(double (&out)[NEN][3])
 // K = cof(J) = J_p J^{-T} and r = 1 / J_p; REL as for grad_field.  Evaluated at every point from
 // all nodes: straight-sided elements have a constant J only up to the
 // rounding of their mid-edge coordinates, which the bulk response amplifies.
-template <int ELEM, int Q, int NEN, bool REL = false>
-__device__ __forceinline__ void ref_geometry(const double *__restrict__ sX, const int (&na)[NEN], m3 &K,
+template <int ELEM, int NEN, bool REL = false, class QT>
+__device__ __forceinline__ void ref_geometry(QT q, const double *__restrict__ sX, const int (&na)[NEN], m3 &K,
                                              double &detJ, double &r)
 {
     m3 J;
-    grad_field<ELEM, Q, NEN, REL>(sX, na, J);
+    grad_field<ELEM, NEN, REL>(q, sX, na, J);
     cofactor(J, K);
     detJ = det_from_cof(J, K);
     r = 1.0 / detJ;
@@ -585,21 +756,20 @@ __device__ __forceinline__ void fwd_element(const double *sm, const int (&na)[NE
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpFwd, DAMPED, MODE>;
-    point_loop<E::nq>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
+    for_points<ELEM>([&](auto q) {
         qp_fence();
         m3 K, G, F, Fd, P, Qm;
         double detJ, r;
-        ref_geometry<ELEM, q, NEN, true>(sm + R::oX, na, K, detJ, r);
-        grad_field<ELEM, q, NEN, true>(sm + R::ox, na, G);
+        ref_geometry<ELEM, NEN, true>(q, sm + R::oX, na, K, detJ, r);
+        grad_field<ELEM, NEN, true>(q, sm + R::ox, na, G);
         to_reference(G, K, r, F);                   // F = N H
         if constexpr (DAMPED) {
-            grad_field<ELEM, q>(sm + R::ov, na, G);
+            grad_field<ELEM, NEN>(q, sm + R::ov, na, G);
             to_reference(G, K, r, Fd);              // Fdot = Ndot H
         }
         stress<LAW, DAMPED>(F, Fd, mt, P);
-        to_parent(P, K, E::weight(q), Qm);
-        scatter_grad<ELEM, q>(Qm, fe);
+        to_parent(P, K, weight_at<ELEM>(q), Qm);
+        scatter_grad<ELEM, NEN>(q, Qm, fe);
     });
 }
 
@@ -624,23 +794,22 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
     // first node there.  The H8 adjoint keeps tile-relative positions (with
     // them its schedule spills hundreds of registers).
     constexpr bool REL = WANT_GT && ELEM == kT10;
-    point_loop<E::nq>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
+    for_points<ELEM>([&](auto q) {
         m3 K, G, F, Gw, Fb;
         double detJ, r;
-        ref_geometry<ELEM, q, NEN, REL>(sm + R::oX, na, K, detJ, r);
-        grad_field<ELEM, q, NEN, REL>(sm + R::ox, na, G);
+        ref_geometry<ELEM, NEN, REL>(q, sm + R::oX, na, K, detJ, r);
+        grad_field<ELEM, NEN, REL>(q, sm + R::ox, na, G);
         to_reference(G, K, r, F);
-        grad_field<ELEM, q>(sm + R::o2, na, G);
+        grad_field<ELEM, NEN>(q, sm + R::o2, na, G);
         to_reference(G, K, r, Gw);
-        const double c = E::weight(q) * detJ;
+        const double c = weight_at<ELEM>(q) * detJ;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) Fb[i][j] = 0.0;
         if constexpr (DAMPED) {
             m3 Fd;
-            grad_field<ELEM, q>(sm + R::ov, na, G);
+            grad_field<ELEM, NEN>(q, sm + R::ov, na, G);
             to_reference(G, K, r, Fd);
             s3 Ed;
             {
@@ -662,8 +831,8 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
 #pragma unroll
                     for (int j = 0; j < 3; ++j) A[i][j] = 0.0;
                 acc_mul_ms(F, SvSg, A);              // Fbar_v
-                to_parent(A, K, E::weight(q), T);
-                scatter_grad<ELEM, q, NEN, DAMPED ? 1 : 0>(T, gv);
+                to_parent(A, K, weight_at<ELEM>(q), T);
+                scatter_grad<ELEM, NEN, DAMPED ? 1 : 0>(q, T, gv);
             }
         }
         MRState st;
@@ -684,18 +853,18 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
         // K is formed again here rather than kept live across the
         // elastic derivative (fewer registers at its peak)
         m3 Qm;
-        {
+        if constexpr (ELEM == kQ27) {
+            to_parent(Fb, K, weight_at<ELEM>(q), Qm);
+        } else {
             m3 K2;
             double d2, r2;
-            ref_geometry<ELEM, q, NEN, REL>(sm + R::oX, na, K2, d2, r2);
-            to_parent(Fb, K2, E::weight(q), Qm);
+            ref_geometry<ELEM, NEN, REL>(q, sm + R::oX, na, K2, d2, r2);
+            to_parent(Fb, K2, weight_at<ELEM>(q), Qm);
         }
-        scatter_grad<ELEM, q, NEN, DAMPED ? 1 : 0>(Qm, gx);
+        scatter_grad<ELEM, NEN, (DAMPED || ELEM == kQ27) ? 1 : 0>(q, Qm, gx);
     });
-    if constexpr (DAMPED) {
-        finish_last_node(gx);
-        finish_last_node(gv);
-    }
+    if constexpr (DAMPED || ELEM == kQ27) finish_last_node(gx);
+    if constexpr (DAMPED) finish_last_node(gv);
 }
 
 // Tangent: dF = sum_a dx_a h_a^T, dFdot = sum_a dv_a h_a^T,
@@ -708,15 +877,14 @@ __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NE
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpJvp, DAMPED>;
-    point_loop<E::nq>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
+    for_points<ELEM>([&](auto q) {
         qp_fence();
         m3 K, G, F, dF, dP;
         double detJ, r;
-        ref_geometry<ELEM, q>(sm + R::oX, na, K, detJ, r);
-        grad_field<ELEM, q>(sm + R::ox, na, G);
+        ref_geometry<ELEM, NEN>(q, sm + R::oX, na, K, detJ, r);
+        grad_field<ELEM, NEN>(q, sm + R::ox, na, G);
         to_reference(G, K, r, F);
-        grad_field<ELEM, q>(sm + R::o2, na, G);
+        grad_field<ELEM, NEN>(q, sm + R::o2, na, G);
         to_reference(G, K, r, dF);
         {
             MRState st;
@@ -725,7 +893,7 @@ __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NE
         }
         if constexpr (DAMPED) {
             m3 Fd, Ed, Sv, A, B, T;
-            grad_field<ELEM, q>(sm + R::ov, na, G);
+            grad_field<ELEM, NEN>(q, sm + R::ov, na, G);
             to_reference(G, K, r, Fd);
             if constexpr (DT) {
                 stress<LAW, true>(F, Fd, dmt, T);
@@ -744,7 +912,7 @@ __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NE
             mTm(dF, Fd, A);                       // dF^T Fdot
             {
                 m3 dFd;
-                grad_field<ELEM, q>(sm + R::odv, na, G);
+                grad_field<ELEM, NEN>(q, sm + R::odv, na, G);
                 to_reference(G, K, r, dFd);
                 mTm(F, dFd, B);                   // F^T dFdot
 #pragma unroll
@@ -771,8 +939,8 @@ __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NE
                 for (int j = 0; j < 3; ++j) dP[i][j] += T[i][j];
         }
         m3 Qm;
-        to_parent(dP, K, E::weight(q), Qm);
-        scatter_grad<ELEM, q>(Qm, df);
+        to_parent(dP, K, weight_at<ELEM>(q), Qm);
+        scatter_grad<ELEM, NEN>(q, Qm, df);
     });
 }
 
@@ -785,6 +953,48 @@ template <int ELEM, int NEN>
 __device__ __forceinline__ void mass_element(const double *su, const int (&na)[NEN], const double *coef,
                                              int64_t stride, double scale, double (&fe)[NEN][3])
 {
+    if constexpr (ELEM == kQ27) {
+        // the stiffness rule; s_ijk = L_i L_j L_k, contracted one direction
+        // at a time in both products
+#pragma nounroll
+        for (int q = 0; q < 27; ++q) {
+            qp_fence();
+            const Q27Pt t = q27_point(q);
+            double u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double uk[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double uj[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) uj[c] += t.L[0][i] * su[na[i + 3 * j + 9 * k] + c];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) uk[c] += t.L[1][j] * uj[c];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) u[c] += t.L[2][k] * uk[c];
+            }
+            const double cq = __builtin_nontemporal_load(coef + q * stride) * scale;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) u[c] *= cq;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double v[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) v[c] = t.L[2][k] * t.L[1][j] * u[c];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) fe[i + 3 * j + 9 * k][c] += t.L[0][i] * v[c];
+                }
+        }
+        return;
+    } else {
     using M = MassRule<ELEM>;
     point_loop<M::nq>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -813,6 +1023,7 @@ __device__ __forceinline__ void mass_element(const double *su, const int (&na)[N
             }
         });
     });
+    }
 }
 
 // ------------------------------------------------------------- tile plumbing
@@ -852,8 +1063,9 @@ __device__ __forceinline__ double field_value(int f, int cc, int64_t g, const Ca
     return c.dv ? c.dv[i] : 0.0;
 }
 
-// Stage the tile's node records.  The host caps a tile at kStagePerThread x
-// (threads) nodes; every load of a thread is issued before its LDS stores.
+// Stage the tile's node records.  The host caps a tile at SPT x (threads)
+// nodes; every load of a thread's round of nodes is issued before its LDS
+// stores (one round for T10 and H8, two for Q27).
 // Reference and current positions are staged relative to the tile's
 // reference node (the one nearest the tile's centroid): the kinematics only
 // use differences of nodal positions (the parent
@@ -873,49 +1085,54 @@ __device__ __forceinline__ double field_value(int f, int cc, int64_t g, const Ca
 // are read in the tile's sorted node order (coalesced) and each record goes
 // to the node's LDS position, which the host chose to spread the per-point
 // gathers of a wavefront over the LDS banks.
-template <int OP, bool DAMPED, int MODE = kModePlain, bool RAW = false>
+template <int OP, bool DAMPED, int MODE = kModePlain, bool RAW = false, int SPT = kStagePerThread>
 __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMesh &m, const CallArgs &c,
                                            const TileDesc &t, int tid, int nthr)
 {
     using R = Rec<OP, DAMPED, MODE>;
     constexpr int nf = R::nfield;
+    constexpr int CH = SPT < kStageRound ? SPT : kStageRound;   // nodes per thread per round
+    static_assert(SPT % CH == 0, "staging rounds");
     const int32_t *gid = m.lnode_gid + t.node_begin;
     const uint16_t *lpos = m.lnode_pos + t.node_begin;
     const int64_t n = m.n_nodes;
     const int g0 = gid[t.ref];
-    int g[kStagePerThread], p[kStagePerThread];
 #pragma unroll
-    for (int k = 0; k < kStagePerThread; ++k) {
-        const int l = tid + k * nthr;
-        g[k] = l < t.n_node ? __builtin_nontemporal_load(gid + l) : -1;
-        p[k] = l < t.n_node ? (int)__builtin_nontemporal_load(lpos + l) : 0;
-    }
-    double v[kStagePerThread][3 * R::nfield];
+    for (int k0 = 0; k0 < SPT; k0 += CH) {
+        int g[CH], p[CH];
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-        const double *xt = m.Xt + cc * m.n_tnode + t.node_begin;
-#pragma unroll
-        for (int k = 0; k < kStagePerThread; ++k)
-            v[k][R::oX + cc] = g[k] >= 0 ? __builtin_nontemporal_load(xt + tid + k * nthr) : 0.0;
-    }
-#pragma unroll
-    for (int f = 1; f < nf; ++f) {
-        const bool centre = !RAW && f == R::ox / 3;
+        for (int k = 0; k < CH; ++k) {
+            const int l = tid + (k0 + k) * nthr;
+            g[k] = l < t.n_node ? __builtin_nontemporal_load(gid + l) : -1;
+            p[k] = l < t.n_node ? (int)__builtin_nontemporal_load(lpos + l) : 0;
+        }
+        double v[CH][3 * R::nfield];
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
-            const double o = centre ? field_value<OP, DAMPED, MODE>(f, cc, g0, c, n) : 0.0;
+            const double *xt = m.Xt + cc * m.n_tnode + t.node_begin;
 #pragma unroll
-            for (int k = 0; k < kStagePerThread; ++k)
-                v[k][3 * f + cc] = g[k] >= 0 ? field_value<OP, DAMPED, MODE>(f, cc, g[k], c, n) - o : 0.0;
+            for (int k = 0; k < CH; ++k)
+                v[k][R::oX + cc] = g[k] >= 0 ? __builtin_nontemporal_load(xt + tid + (k0 + k) * nthr) : 0.0;
         }
+#pragma unroll
+        for (int f = 1; f < nf; ++f) {
+            const bool centre = !RAW && f == R::ox / 3;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                const double o = centre ? field_value<OP, DAMPED, MODE>(f, cc, g0, c, n) : 0.0;
+#pragma unroll
+                for (int k = 0; k < CH; ++k)
+                    v[k][3 * f + cc] = g[k] >= 0 ? field_value<OP, DAMPED, MODE>(f, cc, g[k], c, n) - o : 0.0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+            if (g[k] >= 0) {
+                double *d = sm + (int64_t)p[k] * R::len;
+#pragma unroll
+                for (int j = 0; j < 3 * nf; ++j) d[j] = v[k][j];
+            }
     }
-#pragma unroll
-    for (int k = 0; k < kStagePerThread; ++k)
-        if (g[k] >= 0) {
-            double *d = sm + (int64_t)p[k] * R::len;
-#pragma unroll
-            for (int j = 0; j < 3 * nf; ++j) d[j] = v[k][j];
-        }
 }
 
 // Record offsets of the lane's element nodes (local connectivity [nen][te]).
@@ -952,19 +1169,19 @@ __device__ __forceinline__ TileCsr csr_layout(double *smem, int nl, int rec_len,
 // tables are read once per call and loaded non-temporally.  The slot ids
 // are copied as 32-bit words; a tile's entries start at an even global
 // index (the host pads every tile's list to an even length).
-template <int NEN>
+template <int NEN, int SPT = kStagePerThread>
 __device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, const TileDesc &t, int tid, int nthr)
 {
     const int32_t *gptr = m.lnode_ptr + t.ptr_begin;
     const int32_t base = gptr[0];
-    int32_t pv[kStagePerThread + 1], dv[kStagePerThread];
+    int32_t pv[SPT + 1], dv[SPT];
 #pragma unroll
-    for (int k = 0; k <= kStagePerThread; ++k) {
+    for (int k = 0; k <= SPT; ++k) {
         const int l = tid + k * nthr;
         pv[k] = l <= t.n_node ? __builtin_nontemporal_load(gptr + l) - base : 0;
     }
 #pragma unroll
-    for (int k = 0; k < kStagePerThread; ++k) {
+    for (int k = 0; k < SPT; ++k) {
         const int l = tid + k * nthr;
         dv[k] = l < t.n_node ? __builtin_nontemporal_load(m.lnode_dst + t.node_begin + l) : 0;
     }
@@ -979,10 +1196,10 @@ __device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, co
         wv[k] = e < n_words ? __builtin_nontemporal_load(gw + e) : 0u;
     }
 #pragma unroll
-    for (int k = 0; k <= kStagePerThread; ++k)
+    for (int k = 0; k <= SPT; ++k)
         if (tid + k * nthr <= t.n_node) c.ptr[tid + k * nthr] = pv[k];
 #pragma unroll
-    for (int k = 0; k < kStagePerThread; ++k)
+    for (int k = 0; k < SPT; ++k)
         if (tid + k * nthr < t.n_node) c.dst[tid + k * nthr] = dv[k];
     uint32_t *sw = reinterpret_cast<uint32_t *>(c.slot);
 #pragma unroll
@@ -1110,8 +1327,8 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     // tiles on the compute unit compute
     __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
-    stage_csr<NEN>(csr, m, t, tid, te);
-    stage_tile<kOpFwd, DAMPED, MODE, true>(smem, m, c, t, tid, te);
+    stage_csr<NEN, stage_per_thread(ELEM)>(csr, m, t, tid, te);
+    stage_tile<kOpFwd, DAMPED, MODE, true, stage_per_thread(ELEM)>(smem, m, c, t, tid, te);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double fe[NEN][3];
@@ -1148,8 +1365,8 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     // tiles on the compute unit compute
     __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
-    stage_csr<NEN>(csr, m, t, tid, te);
-    stage_tile<kOpVjp, DAMPED, kModePlain, WANT_GT && ELEM == kT10>(smem, m, c, t, tid, te);
+    stage_csr<NEN, stage_per_thread(ELEM)>(csr, m, t, tid, te);
+    stage_tile<kOpVjp, DAMPED, kModePlain, WANT_GT && ELEM == kT10, stage_per_thread(ELEM)>(smem, m, c, t, tid, te);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double gx[NEN][3], gv[NEN][3], gt[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1202,8 +1419,8 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     // tiles on the compute unit compute
     __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
-    stage_csr<NEN>(csr, m, t, tid, te);
-    stage_tile<kOpJvp, DAMPED, MODE>(smem, m, c, t, tid, te);
+    stage_csr<NEN, stage_per_thread(ELEM)>(csr, m, t, tid, te);
+    stage_tile<kOpJvp, DAMPED, MODE, false, stage_per_thread(ELEM)>(smem, m, c, t, tid, te);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double df[NEN][3];
@@ -1237,24 +1454,25 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_mass(DevMesh m, CallArgs c, in
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
     const TileCsr csr = csr_layout(smem, nl, LEN, NEN, te, nc);
-    stage_csr<NEN>(csr, m, t, tid, te);
+    constexpr int SPT = stage_per_thread(ELEM);
+    stage_csr<NEN, SPT>(csr, m, t, tid, te);
     {
         const int32_t *gid = m.lnode_gid + t.node_begin;
         const uint16_t *lpos = m.lnode_pos + t.node_begin;
-        int g[kStagePerThread], p[kStagePerThread];
-        double v[kStagePerThread][3];
+        int g[SPT], p[SPT];
+        double v[SPT][3];
 #pragma unroll
-        for (int k = 0; k < kStagePerThread; ++k) {
+        for (int k = 0; k < SPT; ++k) {
             const int l = tid + k * te;
             g[k] = l < t.n_node ? __builtin_nontemporal_load(gid + l) : -1;
             p[k] = l < t.n_node ? (int)__builtin_nontemporal_load(lpos + l) : 0;
         }
 #pragma unroll
-        for (int k = 0; k < kStagePerThread; ++k)
+        for (int k = 0; k < SPT; ++k)
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) v[k][cc] = g[k] >= 0 ? c.x[cc * m.n_nodes + g[k]] : 0.0;
 #pragma unroll
-        for (int k = 0; k < kStagePerThread; ++k)
+        for (int k = 0; k < SPT; ++k)
             if (g[k] >= 0)
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) smem[p[k] * LEN + cc] = v[k][cc];
@@ -1290,18 +1508,17 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_inverted(DevMesh m, CallArgs c
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x;
-    stage_tile<kOpFwd, false, kModePlain, true>(smem, m, c, t, tid, te);
+    stage_tile<kOpFwd, false, kModePlain, true, stage_per_thread(ELEM)>(smem, m, c, t, tid, te);
     __syncthreads();
     int n = 0;
     if (tid < t.n_elem) {
         int na[NEN];
         load_na<NEN, R::len>(m, t, tid, te, na);
-        point_loop<E::nq>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
+        for_points<ELEM>([&](auto q) {
             m3 K, G, F, cof;
             double detJ, r;
-            ref_geometry<ELEM, q, NEN, true>(smem + R::oX, na, K, detJ, r);
-            grad_field<ELEM, q, NEN, true>(smem + R::ox, na, G);
+            ref_geometry<ELEM, NEN, true>(q, smem + R::oX, na, K, detJ, r);
+            grad_field<ELEM, NEN, true>(q, smem + R::ox, na, G);
             to_reference(G, K, r, F);
             cofactor(F, cof);
             n += det_from_cof(F, cof) <= 0.0 ? 1 : 0;

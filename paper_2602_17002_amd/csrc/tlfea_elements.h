@@ -12,7 +12,7 @@
 
 namespace tlfea {
 
-enum { kT10 = 0, kH8 = 1 };
+enum { kT10 = 0, kH8 = 1, kQ27 = 2 };
 
 template <int ELEM> struct ElemDef;
 
@@ -69,8 +69,9 @@ template <> struct ElemDef<kT10> {
         default: return 4 * y * z;
         }
     }
-    // corners used to decide whether the parent-to-reference map is affine
+    // the four corner nodes (the first four)
     static constexpr int n_corner = 4;
+    static constexpr TLFEA_HD int corner(int c) { return c; }
 };
 
 // 8-node trilinear hexahedron on [-1,1]^3 (not in the paper), nodes
@@ -98,6 +99,48 @@ template <> struct ElemDef<kH8> {
         return 0.125 * (1.0 + sgn(a, 0) * x) * (1.0 + sgn(a, 1) * y) * (1.0 + sgn(a, 2) * z);
     }
     static constexpr int n_corner = 8;
+    static constexpr TLFEA_HD int corner(int c) { return c; }
+};
+
+// 27-node triquadratic hexahedron on [-1,1]^3 (App. A): node n = i + 3 j +
+// 9 k at parent (i - 1, j - 1, k - 1), i fastest; s_n = L_i(xi) L_j(eta)
+// L_k(zeta) with the 1-D quadratic Lagrange polynomials L_0(s) = s (s - 1) / 2,
+// L_1(s) = 1 - s^2, L_2(s) = s (s + 1) / 2.  Quadrature: 3x3x3 Gauss-Legendre
+// (points 0, +-sqrt(3/5), weights 8/9, 5/9), point q = p0 + 3 p1 + 9 p2 in the
+// node order.  The kernels do not unroll over its 27 x 27 gradient table:
+// they loop over the points at run time and contract the 1-D values of
+// each point (lag1 / dlag1 at gauss(p)) one direction at a time.
+template <> struct ElemDef<kQ27> {
+    static constexpr int nen = 27, nq = 27;
+    static constexpr double g = 0.77459666924148337704;   // sqrt(3/5)
+    static constexpr TLFEA_HD double gauss(int p) { return p == 0 ? -g : (p == 1 ? 0.0 : g); }
+    static constexpr TLFEA_HD double gauss_w(int p) { return p == 1 ? 8.0 / 9.0 : 5.0 / 9.0; }
+    static constexpr TLFEA_HD double lag1(int i, double s)
+    {
+        return i == 0 ? 0.5 * s * (s - 1.0) : (i == 1 ? 1.0 - s * s : 0.5 * s * (s + 1.0));
+    }
+    static constexpr TLFEA_HD double dlag1(int i, double s) { return i == 0 ? s - 0.5 : (i == 1 ? -2.0 * s : s + 0.5); }
+    static constexpr TLFEA_HD int digit(int n, int k) { return k == 0 ? n % 3 : (k == 1 ? (n / 3) % 3 : n / 9); }
+    static constexpr TLFEA_HD double qp(int q, int k) { return gauss(digit(q, k)); }
+    static constexpr TLFEA_HD double weight(int q)
+    {
+        return gauss_w(digit(q, 0)) * gauss_w(digit(q, 1)) * gauss_w(digit(q, 2));
+    }
+    static constexpr TLFEA_HD double grad_at(int a, int k, double x, double y, double z)
+    {
+        const double p[3] = {x, y, z};
+        double r = 1.0;
+        for (int j = 0; j < 3; ++j) r *= j == k ? dlag1(digit(a, j), p[j]) : lag1(digit(a, j), p[j]);
+        return r;
+    }
+    static constexpr TLFEA_HD double grad(int q, int a, int k) { return grad_at(a, k, qp(q, 0), qp(q, 1), qp(q, 2)); }
+    static constexpr TLFEA_HD double shape_at(int a, double x, double y, double z)
+    {
+        return lag1(digit(a, 0), x) * lag1(digit(a, 1), y) * lag1(digit(a, 2), z);
+    }
+    // the eight corner nodes (i, j, k in {0, 2})
+    static constexpr int n_corner = 8;
+    static constexpr TLFEA_HD int corner(int c) { return 2 * (c & 1) + 6 * ((c >> 1) & 1) + 18 * (c >> 2); }
 };
 
 // Quadrature of the consistent mass m_ij = int rho s_i s_j dV_r (Sec. 4.1),
@@ -148,6 +191,16 @@ template <> struct MassRule<kH8> {
     static constexpr TLFEA_HD double weight(int q) { return ElemDef<kH8>::weight(q); }
     static constexpr TLFEA_HD double shape(int q, int a) { return ElemDef<kH8>::shape_at(a, qp(q, 0), qp(q, 1), qp(q, 2)); }
     static constexpr TLFEA_HD double grad(int q, int a, int k) { return ElemDef<kH8>::grad(q, a, k); }
+};
+
+// Q27: the stiffness rule (3x3x3 Gauss, exact for the mass integrand of a
+// straight-sided element, degree 4 per direction).
+template <> struct MassRule<kQ27> {
+    static constexpr int nq = 27;
+    static constexpr TLFEA_HD double qp(int q, int k) { return ElemDef<kQ27>::qp(q, k); }
+    static constexpr TLFEA_HD double weight(int q) { return ElemDef<kQ27>::weight(q); }
+    static constexpr TLFEA_HD double shape(int q, int a) { return ElemDef<kQ27>::shape_at(a, qp(q, 0), qp(q, 1), qp(q, 2)); }
+    static constexpr TLFEA_HD double grad(int q, int a, int k) { return ElemDef<kQ27>::grad(q, a, k); }
 };
 
 }  // namespace tlfea

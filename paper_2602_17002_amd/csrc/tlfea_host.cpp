@@ -30,15 +30,21 @@ TLFEA_DECL(0, 0, 0, 0) TLFEA_DECL(0, 0, 0, 1) TLFEA_DECL(0, 1, 0, 0) TLFEA_DECL(
 TLFEA_DECL(0, 2, 0, 0) TLFEA_DECL(0, 2, 0, 1)
 TLFEA_DECL(1, 0, 0, 0) TLFEA_DECL(1, 0, 0, 1) TLFEA_DECL(1, 1, 0, 0) TLFEA_DECL(1, 1, 1, 0)
 TLFEA_DECL(1, 2, 0, 0) TLFEA_DECL(1, 2, 0, 1)
+TLFEA_DECL(2, 0, 0, 0) TLFEA_DECL(2, 0, 0, 1) TLFEA_DECL(2, 1, 0, 0) TLFEA_DECL(2, 1, 1, 0)
+TLFEA_DECL(2, 2, 0, 0) TLFEA_DECL(2, 2, 0, 1)
 #undef TLFEA_DECL
 hipError_t launch_mass_e0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
                           int tile0, int nl, int nc);
 hipError_t launch_mass_e1(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
                           int tile0, int nl, int nc);
+hipError_t launch_mass_e2(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
+                          int tile0, int nl, int nc);
 hipError_t launch_halo(hipStream_t s, const DevMesh &m, double *out0, double *out1, const double *sub);
 hipError_t launch_inverted_e0_o0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
                                  int tile0, unsigned long long *count);
 hipError_t launch_inverted_e1_o0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
+                                 int tile0, unsigned long long *count);
+hipError_t launch_inverted_e2_o0(int te, int n_tiles, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c,
                                  int tile0, unsigned long long *count);
 hipError_t launch_zero_count(hipStream_t s, unsigned long long *count);
 hipError_t scratch_address(double **out);
@@ -73,14 +79,17 @@ static hipError_t launch_tiles(int elem, int law, int damped, int te, int kind, 
                                int);
     // per element type: forward, adjoint, tangent, step residual, Newton
     // operator, and the adjoint with the parameter gradients
-    static const fn_t table[2][6] = {
+    static const fn_t table[3][6] = {
         {launch_tiles_e0_o0_g0_m0, launch_tiles_e0_o1_g0_m0, launch_tiles_e0_o2_g0_m0, launch_tiles_e0_o0_g0_m1,
          launch_tiles_e0_o2_g0_m1, launch_tiles_e0_o1_g1_m0},
         {launch_tiles_e1_o0_g0_m0, launch_tiles_e1_o1_g0_m0, launch_tiles_e1_o2_g0_m0, launch_tiles_e1_o0_g0_m1,
-         launch_tiles_e1_o2_g0_m1, launch_tiles_e1_o1_g1_m0}};
-    if (elem < 0 || elem > 1) return hipErrorInvalidValue;
-    if (kind == kKMass)
-        return (elem == 0 ? launch_mass_e0 : launch_mass_e1)(te, n_tiles, lds, s, m, c, tile0, nl, nc);
+         launch_tiles_e1_o2_g0_m1, launch_tiles_e1_o1_g1_m0},
+        {launch_tiles_e2_o0_g0_m0, launch_tiles_e2_o1_g0_m0, launch_tiles_e2_o2_g0_m0, launch_tiles_e2_o0_g0_m1,
+         launch_tiles_e2_o2_g0_m1, launch_tiles_e2_o1_g1_m0}};
+    typedef hipError_t (*mass_t)(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int, int);
+    static const mass_t mass[3] = {launch_mass_e0, launch_mass_e1, launch_mass_e2};
+    if (elem < 0 || elem > 2) return hipErrorInvalidValue;
+    if (kind == kKMass) return mass[elem](te, n_tiles, lds, s, m, c, tile0, nl, nc);
     int k;
     switch (kind) {
     case kKFwd: k = 0; break;
@@ -123,29 +132,68 @@ extern "C" const char *tlfea_last_error(void) { return g_err.c_str(); }
 
 // ------------------------------------------------------------------ element data (host)
 
-static int nen_of(int elem) { return elem == kT10 ? ElemDef<kT10>::nen : ElemDef<kH8>::nen; }
-static int nq_of(int elem) { return elem == kT10 ? ElemDef<kT10>::nq : ElemDef<kH8>::nq; }
-static int ncorner_of(int elem) { return elem == kT10 ? ElemDef<kT10>::n_corner : ElemDef<kH8>::n_corner; }
+// Parent-element tables of one element type (T10, H8 or Q27), evaluated
+// once from the constexpr definitions of tlfea_elements.h: the gradients
+// and weights of the internal-force rule and of the mass rule.
+struct ElemTables {
+    int nen = 0, nq = 0, nqm = 0, ncorner = 0;
+    std::vector<double> grad, w, mgrad, mw;   // grad[(q * nen + a) * 3 + k]
+    std::vector<int> corner;
+};
+
+template <int ELEM>
+static ElemTables make_tables()
+{
+    using E = ElemDef<ELEM>;
+    using M = MassRule<ELEM>;
+    ElemTables t;
+    t.nen = E::nen;
+    t.nq = E::nq;
+    t.nqm = M::nq;
+    t.ncorner = E::n_corner;
+    for (int q = 0; q < E::nq; ++q) {
+        t.w.push_back(E::weight(q));
+        for (int a = 0; a < E::nen; ++a)
+            for (int k = 0; k < 3; ++k) t.grad.push_back(E::grad(q, a, k));
+    }
+    for (int q = 0; q < M::nq; ++q) {
+        t.mw.push_back(M::weight(q));
+        for (int a = 0; a < E::nen; ++a)
+            for (int k = 0; k < 3; ++k) t.mgrad.push_back(M::grad(q, a, k));
+    }
+    for (int c = 0; c < E::n_corner; ++c) t.corner.push_back(E::corner(c));
+    return t;
+}
+
+static const ElemTables &tables_of(int elem)
+{
+    static const ElemTables t10 = make_tables<kT10>(), h8 = make_tables<kH8>(), q27 = make_tables<kQ27>();
+    return elem == kT10 ? t10 : (elem == kH8 ? h8 : q27);
+}
+static int nen_of(int elem) { return tables_of(elem).nen; }
+static int nq_of(int elem) { return tables_of(elem).nq; }
+static int ncorner_of(int elem) { return tables_of(elem).ncorner; }
+static int corner_of(int elem, int c) { return tables_of(elem).corner[c]; }
 static double grad_of(int elem, int q, int a, int k)
 {
-    return elem == kT10 ? ElemDef<kT10>::grad(q, a, k) : ElemDef<kH8>::grad(q, a, k);
+    const ElemTables &t = tables_of(elem);
+    return t.grad[((size_t)q * t.nen + a) * 3 + k];
 }
 static double shape_of(int elem, int a, const double *xi)
 {
-    return elem == kT10 ? ElemDef<kT10>::shape_at(a, xi[0], xi[1], xi[2]) : ElemDef<kH8>::shape_at(a, xi[0], xi[1], xi[2]);
+    switch (elem) {
+    case kT10: return ElemDef<kT10>::shape_at(a, xi[0], xi[1], xi[2]);
+    case kH8: return ElemDef<kH8>::shape_at(a, xi[0], xi[1], xi[2]);
+    default: return ElemDef<kQ27>::shape_at(a, xi[0], xi[1], xi[2]);
+    }
 }
-static double weight_of(int elem, int q)
-{
-    return elem == kT10 ? ElemDef<kT10>::weight(q) : ElemDef<kH8>::weight(q);
-}
-static int nqm_of(int elem) { return elem == kT10 ? MassRule<kT10>::nq : MassRule<kH8>::nq; }
-static double mass_weight_of(int elem, int q)
-{
-    return elem == kT10 ? MassRule<kT10>::weight(q) : MassRule<kH8>::weight(q);
-}
+static double weight_of(int elem, int q) { return tables_of(elem).w[q]; }
+static int nqm_of(int elem) { return tables_of(elem).nqm; }
+static double mass_weight_of(int elem, int q) { return tables_of(elem).mw[q]; }
 static double mass_grad_of(int elem, int q, int a, int k)
 {
-    return elem == kT10 ? MassRule<kT10>::grad(q, a, k) : MassRule<kH8>::grad(q, a, k);
+    const ElemTables &t = tables_of(elem);
+    return t.mgrad[((size_t)q * t.nen + a) * 3 + k];
 }
 
 // ------------------------------------------------------------------ mesh object
@@ -175,7 +223,7 @@ struct tlfea_mesh {
     int n_blocks = 0;
     std::vector<BlockDesc> blocks;
     std::vector<ClassRange> classes;
-    int te_t10 = 0, te_h8 = 0;
+    int te_t10 = 0, te_h8 = 0, te_q27 = 0;
     DevMesh dm{};
     std::vector<void *> allocations;
     int64_t device_bytes = 0;
@@ -267,7 +315,7 @@ static void block_order(const tlfea_block &b, int64_t n_nodes, const double *X, 
     for (int64_t e = 0; e < ne; ++e)
         for (int k = 0; k < 3; ++k) {
             double s = 0;
-            for (int a = 0; a < nc; ++a) s += X[k * n_nodes + b.conn[e * nen + a]] - X[k * n_nodes + g0];
+            for (int a = 0; a < nc; ++a) s += X[k * n_nodes + b.conn[e * nen + corner_of(b.elem, a)]] - X[k * n_nodes + g0];
             s /= nc;
             cen[3 * e + k] = s;
             lo[k] = std::min(lo[k], s);
@@ -335,7 +383,7 @@ struct HostBuild {
 #endif
 constexpr int64_t kOffsetLimit = TLFEA_OFFSET_LIMIT;
 
-static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
+static int default_te(int elem) { return elem == kQ27 ? 64 : 256; }
 
 // Distinct nodes a tile may hold: at most kStagePerThread per thread, and
 // few enough that every operation's node records and assembly tables stay
@@ -348,6 +396,9 @@ static int default_te(int elem) { return elem == kT10 ? 256 : 256; }
 // least two.
 static int64_t lds_budget(int kind, int elem, int law, int damped, int te, int64_t lds_dev)
 {
+    // Q27 tiles hold about 11 nodes per element: two 64-element tiles (one
+    // wave each) per compute unit
+    if (elem == kQ27) return std::min<int64_t>(lds_dev, 163840 / std::max(1, 128 / te));
     const int op = kind_op(kind), mode = kind_mode(kind);
     const int64_t waves_per_cu =
         kind == kKFwd ? 12 : (kind == kKMass ? 16 : 4 * std::max(2, waves_per_simd(op, elem, law, damped != 0, mode)));
@@ -360,13 +411,13 @@ static int kind_record_len(int kind, bool damped) { return record_len(kind_op(ki
 static int nl_limit(int elem, int law, int te, int damped, int64_t lds_dev)
 {
     const int nen = nen_of(elem);
-    int64_t nl = (int64_t)kStagePerThread * te;
+    int64_t nl = (int64_t)stage_per_thread(elem) * te;
     // full 256-element tiles: at most 600 nodes even where the LDS would hold
     // more.  Compact T10 tiles have about 550 (p99 670 without the cap), and
     // letting the ragged ones grow further made the undamped forward 8 %
     // slower.  Smaller tiles have proportionally more surface nodes and keep
     // only the LDS limit.
-    if (te == 256) nl = std::min<int64_t>(nl, 600);
+    if (te == 256 && elem != kQ27) nl = std::min<int64_t>(nl, 600);
     for (int kind : kKinds) {
         const int64_t fixed = 4 + (int64_t)nen * te * 2;
         const int64_t per_node = 8 * (int64_t)kind_record_len(kind, damped != 0) + 8;
@@ -479,7 +530,8 @@ static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const double *X, c
     for (int64_t j = 0; j < ne; ++j)
         for (int k = 0; k < 3; ++k) {
             double s = 0;
-            for (int a = 0; a < ncn; ++a) s += X[k * n_nodes + B.conn[ids[j] * nen + a]] - X[k * n_nodes + g0];
+            for (int a = 0; a < ncn; ++a)
+                s += X[k * n_nodes + B.conn[ids[j] * nen + corner_of(B.elem, a)]] - X[k * n_nodes + g0];
             cen[3 * j + k] = s / ncn;
         }
     // node -> elements (positions in ids)
@@ -718,7 +770,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                 t.conn_begin = (int32_t)hb.conn_local.size();
                 t.block = b;
                 t.ref = 0;
-                if (t.n_node > nlmax || t.n_node > kStagePerThread * te)
+                if (t.n_node > nlmax || t.n_node > stage_per_thread(B.elem) * te)
                     return fail(TLFEA_E_UNSUPPORTED, "tile with %d nodes exceeds the limit %d", t.n_node, nlmax);
                 for (size_t l = 0; l < nodes.size(); ++l) {
                     local[nodes[l]] = (int32_t)l;
@@ -868,13 +920,16 @@ static tlfea_status validate_args(int64_t n_nodes, const double *X, int32_t n_bl
     int64_t total = 0;
     for (int b = 0; b < n_blocks; ++b) {
         const tlfea_block &B = blocks[b];
-        if (B.elem != TLFEA_T10 && B.elem != TLFEA_H8) return fail(TLFEA_E_INVALID, "block %d: unknown element %d", b, B.elem);
+        if (B.elem != TLFEA_T10 && B.elem != TLFEA_H8 && B.elem != TLFEA_Q27)
+            return fail(TLFEA_E_INVALID, "block %d: unknown element %d", b, B.elem);
         if (B.law != TLFEA_SVK && B.law != TLFEA_MR && B.law != TLFEA_NH)
             return fail(TLFEA_E_INVALID, "block %d: unknown law %d", b, B.law);
         if (B.n_elem < 0) return fail(TLFEA_E_SHAPE, "block %d: n_elem < 0", b);
         if (B.n_elem > 0 && !B.conn) return fail(TLFEA_E_INVALID, "block %d: conn is NULL", b);
         if (B.tile_elems < 0 || B.tile_elems > 256 || (B.tile_elems & 63))
             return fail(TLFEA_E_INVALID, "block %d: tile_elems must be 0, 64, 128, 192 or 256", b);
+        if (B.elem == TLFEA_Q27 && B.tile_elems > 128)
+            return fail(TLFEA_E_INVALID, "block %d: Q27 tile_elems must be 0, 64 or 128", b);
         for (int p = 0; p < 5; ++p)
             if (!std::isfinite(B.theta[p])) return fail(TLFEA_E_INVALID, "block %d: theta[%d] not finite", b, p);
         if (B.reserved != 0) return fail(TLFEA_E_INVALID, "block %d: reserved field must be 0", b);
@@ -940,6 +995,7 @@ static tlfea_status create_with(int64_t n_nodes, const double *X, int32_t n_bloc
         m->any_damped |= blocks[b].damped != 0;
         if (blocks[b].elem == kT10 && !m->te_t10) m->te_t10 = te_of_block[b];
         if (blocks[b].elem == kH8 && !m->te_h8) m->te_h8 = te_of_block[b];
+        if (blocks[b].elem == kQ27 && !m->te_q27) m->te_q27 = te_of_block[b];
     }
     m->classes = hb.classes;
     m->tile_nodes = hb.lnode_gid;
@@ -1600,8 +1656,10 @@ extern "C" tlfea_status tlfea_count_inverted(tlfea_mesh *m, const double *x, int
     c.x = x;
     for (const ClassRange &cr : m->classes) {
         const size_t lds = (size_t)cr.nl_cap * record_len(kOpFwd, false) * sizeof(double);
-        e = cr.elem == kT10 ? launch_inverted_e0_o0(cr.te, cr.tile_count, lds, s, m->dm, c, cr.tile_begin, cnt)
-                            : launch_inverted_e1_o0(cr.te, cr.tile_count, lds, s, m->dm, c, cr.tile_begin, cnt);
+        typedef hipError_t (*inv_t)(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int,
+                                    unsigned long long *);
+        static const inv_t inv[3] = {launch_inverted_e0_o0, launch_inverted_e1_o0, launch_inverted_e2_o0};
+        e = inv[cr.elem](cr.te, cr.tile_count, lds, s, m->dm, c, cr.tile_begin, cnt);
         if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "kernel launch: %s", hipGetErrorString(e));
     }
     return TLFEA_OK;
@@ -1670,12 +1728,16 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
     // adjoint + tangent time summed over the classes of that type (one size
     // per type, as tlfea_get_mesh_info reports it); blocks that fix
     // tile_elems keep it.
-    const int cand[4] = {64, 128, 192, 256};
-    double best_t[2] = {1e300, 1e300};
-    int best_c[2] = {default_te(kT10), default_te(kH8)};
+    // Q27 tiles take 64 or 128 elements (the LDS of their node records)
+    const int cand[3][4] = {{64, 128, 192, 256}, {64, 128, 192, 256}, {64, 128, 0, 0}};
+    double best_t[3] = {1e300, 1e300, 1e300};
+    int best_c[3] = {default_te(kT10), default_te(kH8), default_te(kQ27)};
     for (int ci = 0; ci < 4; ++ci) {
         std::vector<int> tc(n_blocks);
-        for (int b = 0; b < n_blocks; ++b) tc[b] = blocks[b].tile_elems ? blocks[b].tile_elems : cand[ci];
+        for (int b = 0; b < n_blocks; ++b) {
+            const int e = blocks[b].elem;
+            tc[b] = blocks[b].tile_elems ? blocks[b].tile_elems : (cand[e][ci] ? cand[e][ci] : best_c[e]);
+        }
         tlfea_mesh *m = nullptr;
         st = create_with(n_nodes, X, n_blocks, blocks, flags & ~TLFEA_BATCHED, tc, s, &m);
         if (st) return st;
@@ -1685,12 +1747,12 @@ extern "C" tlfea_status tlfea_create_mesh(int64_t n_nodes, const double *X, int3
             tlfea_destroy_mesh(m);
             return st;
         }
-        double sum[2] = {0.0, 0.0};
+        double sum[3] = {0.0, 0.0, 0.0};
         for (size_t k = 0; k < m->classes.size(); ++k) sum[m->classes[k].elem] += t[k];
-        for (int e = 0; e < 2; ++e)
-            if (sum[e] < best_t[e]) {
+        for (int e = 0; e < 3; ++e)
+            if (cand[e][ci] && sum[e] < best_t[e]) {
                 best_t[e] = sum[e];
-                best_c[e] = cand[ci];
+                best_c[e] = cand[e][ci];
             }
         tlfea_destroy_mesh(m);
     }
@@ -1723,6 +1785,8 @@ extern "C" tlfea_status tlfea_get_mesh_info(const tlfea_mesh *m, tlfea_mesh_info
     info->flags = m->flags;
     info->tile_elems_t10 = m->te_t10;
     info->tile_elems_h8 = m->te_h8;
+    info->tile_elems_q27 = m->te_q27;
+    info->reserved = 0;
     info->device_bytes = m->device_bytes;
     return TLFEA_OK;
 }
@@ -1839,7 +1903,7 @@ extern "C" tlfea_status tlfea_create_joints(int64_t n_nodes, const double *X, in
     for (int64_t j = 0; j < nj; ++j) {
         const tlfea_point *pt[5] = {&joints[j].P, &joints[j].Q, &joints[j].R, &joints[j].S, &joints[j].T};
         for (int p = 0; p < 5; ++p) {
-            if (pt[p]->elem != TLFEA_T10 && pt[p]->elem != TLFEA_H8)
+            if (pt[p]->elem != TLFEA_T10 && pt[p]->elem != TLFEA_H8 && pt[p]->elem != TLFEA_Q27)
                 return fail(TLFEA_E_INVALID, "joint %lld point %d: unknown element type %d", (long long)j, p, pt[p]->elem);
             const int nen = nen_of(pt[p]->elem);
             nmax = std::max(nmax, nen);

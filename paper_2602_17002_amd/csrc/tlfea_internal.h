@@ -20,8 +20,13 @@ struct TileDesc {
 };
 
 // Node records a thread stages at most: a tile holds at most this many
-// nodes per thread of its workgroup.
+// nodes per thread of its workgroup (element types 0, 1: T10, H8, about
+// 2.2 and 1.6 distinct nodes per element in a compact tile; 2: Q27, about
+// 11).  The staging loads are issued in rounds of at most kStageRound nodes
+// per thread.
 constexpr int kStagePerThread = 3;
+constexpr int kStageRound = 6;
+constexpr int stage_per_thread(int elem) { return elem == 2 ? 12 : kStagePerThread; }
 
 struct BlockDesc {
     double theta[5];
@@ -83,11 +88,16 @@ constexpr int kMaxDevices = 64;
 // spills would cost more than the extra wave gains (Mooney-Rivlin, the
 // damped adjoint's two sets of accumulators, the other T10 cases), and the
 // damped Mooney-Rivlin adjoint a whole SIMD's registers.  Laws: 0 SVK,
-// 1 Mooney-Rivlin, 2 Neo-Hookean; element 1 is H8.
+// 1 Mooney-Rivlin, 2 Neo-Hookean; element 1 is H8, 2 is Q27.
 constexpr int waves_per_simd(int op, int elem, int law, bool damped, int mode = 0)
 {
     // the step residual stages the adjoint's record length: its LDS budget
     // is two workgroups per compute unit
+    // Q27: the LDS of a tile's node records (about 11 nodes per element)
+    // allows two or three tiles of one wave per compute unit, so every Q27
+    // kernel takes a whole SIMD's registers (its 81 accumulators per node
+    // field and the element's 27 record offsets stay in registers)
+    if (elem == 2) return 1;
     if (op == kOpFwd) return (law == 1 || mode == 1) ? 2 : 3;
     if (op == kOpVjp && law == 1 && damped) return 1;
     if (damped || law == 1) return 2;

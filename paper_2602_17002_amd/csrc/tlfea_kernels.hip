@@ -1,5 +1,5 @@
 // One translation unit per (element type, operation, variant): compiled
-// with -DTLFEA_ELEM=<0|1> -DTLFEA_OP=<0|1|2> so the instantiations build in
+// with -DTLFEA_ELEM=<0|1|2> -DTLFEA_OP=<0|1|2> so the instantiations build in
 // parallel; the adjoint has two units, -DTLFEA_VJP_GT=<0|1>, and the forward
 // and the tangent two, -DTLFEA_MODE=<0|1> (the plain operation, or the step
 // residual / Newton operator; the step forward unit also holds the mass

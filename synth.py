@@ -323,6 +323,30 @@ def config_c2(seed=1002):
     return p
 
 
+def config_box_q27(nx, ny, nz, seed, cell=0.01, damped=True, name=None, amp=0.02):
+    """Box of Q27 cells under a rigid motion + smooth sinusoid (Neo-Hookean
+    with the C2 moduli, Kelvin-Voigt when damped), with a cotangent w and
+    directions dx, dv."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    X, conn = box_q27(nx, ny, nz, size=(nx * cell, ny * cell, nz * cell))
+    x = sinusoidal_state(X, amp, rng)
+    v = rng.normal(0.0, 0.01, X.shape) if damped else np.zeros_like(X)
+    mu10, k = nh_from_lame(3.4e6, 1.5e7)
+    th = _theta(NH, mu10, 0.0, k, 1e4 if damped else 0.0, 0.0)
+    blk = Block(Q27, NH, conn, th, damped=damped)
+    prob = Problem(name or f"box-{nx}x{ny}x{nz}-Q27-NH", X, x, v, [blk], cell=cell)
+    prob.w = rng.standard_normal(X.shape)
+    prob.dx = rng.standard_normal(X.shape) * cell
+    prob.dv = rng.standard_normal(X.shape)
+    return prob
+
+
+def config_q27(seed=1027):
+    """131,072 Q27 elements (64x64x32 cells of 1 cm, 1,081,665 nodes,
+    3,538,944 points), Neo-Hookean + Kelvin-Voigt as the 1M-element T10 box."""
+    return config_box_q27(64, 64, 32, seed, damped=True, name="Q27-131k-NH-KV")
+
+
 def config_c4(seed=1004):
     """204,000 T10 elements (50x40x17 cells), NH with per-element (mu, lambda)."""
     return config_box_nh(50, 40, 17, seed, damped=False, per_elem=True,

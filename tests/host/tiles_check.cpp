@@ -19,11 +19,15 @@ hipError_t launch_inverted_e0_o0(int, int, size_t, hipStream_t, const DevMesh &,
                                  unsigned long long *) { return hipErrorInvalidValue; }
 hipError_t launch_inverted_e1_o0(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int,
                                  unsigned long long *) { return hipErrorInvalidValue; }
+hipError_t launch_inverted_e2_o0(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int,
+                                 unsigned long long *) { return hipErrorInvalidValue; }
 hipError_t launch_zero_count(hipStream_t, unsigned long long *) { return hipErrorInvalidValue; }
 hipError_t scratch_address(double **) { return hipErrorInvalidValue; }
 hipError_t launch_mass_e0(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int, int)
 { return hipErrorInvalidValue; }
 hipError_t launch_mass_e1(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int, int)
+{ return hipErrorInvalidValue; }
+hipError_t launch_mass_e2(int, int, size_t, hipStream_t, const DevMesh &, const CallArgs &, int, int, int)
 { return hipErrorInvalidValue; }
 hipError_t launch_mdot(const double *, int64_t, int, const double *, int64_t, double *, hipStream_t)
 { return hipErrorInvalidValue; }
@@ -41,6 +45,8 @@ TLFEA_STUB(0, 0, 0, 0) TLFEA_STUB(0, 0, 0, 1) TLFEA_STUB(0, 1, 0, 0) TLFEA_STUB(
 TLFEA_STUB(0, 2, 0, 0) TLFEA_STUB(0, 2, 0, 1)
 TLFEA_STUB(1, 0, 0, 0) TLFEA_STUB(1, 0, 0, 1) TLFEA_STUB(1, 1, 0, 0) TLFEA_STUB(1, 1, 1, 0)
 TLFEA_STUB(1, 2, 0, 0) TLFEA_STUB(1, 2, 0, 1)
+TLFEA_STUB(2, 0, 0, 0) TLFEA_STUB(2, 0, 0, 1) TLFEA_STUB(2, 1, 0, 0) TLFEA_STUB(2, 1, 1, 0)
+TLFEA_STUB(2, 2, 0, 0) TLFEA_STUB(2, 2, 0, 1)
 #undef TLFEA_STUB
 }  // namespace tlfea
 
@@ -125,7 +131,7 @@ int main(int argc, char **argv)
         const TileDesc &t = hb.tiles[ti];
         const int b = t.block, nen = nen_of(blocks[b].elem), T = te[b];
         CHECK(t.n_elem >= 1 && t.n_elem <= T, "tile %zu has %d elements (te %d)", ti, t.n_elem, T);
-        CHECK(t.n_node <= kStagePerThread * T, "tile %zu has %d nodes", ti, t.n_node);
+        CHECK(t.n_node <= stage_per_thread(blocks[b].elem) * T, "tile %zu has %d nodes", ti, t.n_node);
         // sorted unique node ids, positions a permutation
         std::vector<int> pos_seen(t.n_node, 0), local_of_pos(t.n_node, -1);
         for (int l = 0; l < t.n_node; ++l) {

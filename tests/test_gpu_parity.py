@@ -44,7 +44,7 @@ def make_problem(elem, law, damped, n=(7, 5, 3), seed=0, curved=False, per_elem=
     rng = np.random.default_rng(seed)
     lid, th = LAWS[law]
     size = tuple(k * cell for k in n)
-    X, conn = (synth.box_t10 if elem == synth.T10 else synth.box_h8)(*n, size=size)
+    X, conn = {synth.T10: synth.box_t10, synth.H8: synth.box_h8, synth.Q27: synth.box_q27}[elem](*n, size=size)
     if curved:
         if elem == synth.T10:
             X = synth.curve_midside_t10(X, conn, 0.08, rng)

@@ -66,6 +66,18 @@ def test_single_body_tiles(harness, tmp_path, tile):
     assert s["gather_cycles_placed"] < 0.8 * s["gather_cycles_sorted"]
 
 
+@pytest.mark.parametrize("tile", [64, 128])
+def test_q27_body_tiles(harness, tmp_path, tile):
+    """Q27 tiles hold about 11 nodes per element: at most 12 per thread, and
+    the LDS of two 64-element tiles per compute unit; every check of the
+    harness (CSR lists, partials, record positions) holds for 27 nodes."""
+    X, conn = synth.box_q27(9, 8, 7, size=(0.09, 0.08, 0.07))
+    b = synth.Block(synth.Q27, synth.NH, conn, np.array([1.7e6, 0, 1.7e7, 1e4, 0]), damped=True)
+    b.tile_elems = tile
+    s = run(harness, tmp_path, X, [b])
+    assert s["tiles"] >= conn.shape[0] // tile
+
+
 def test_multibody_mixed_blocks_and_keep_order(harness, tmp_path):
     p = synth.config_multibody(6, 150, 2500, seed=21)
     for flags in (0, 4):   # default order, TLFEA_KEEP_ORDER
