@@ -50,61 +50,46 @@ __device__ __forceinline__ void point_loop(Fn &&fn)
     }
 }
 
-// The quadrature points of an element type: T10 and H8 as point_loop
-// (each point a compile-time instance, passed as integral_constant); Q27 as
-// a plain loop whose index is the same in every lane of the wavefront, so
-// that the per-point 1-D tables below are read into scalar registers.
+// The quadrature points a lane evaluates: T10 and H8 every point of its
+// element as point_loop (each point a compile-time instance, passed as
+// integral_constant); Q27 the points part, part + 2, ... of its element (the
+// element's two lanes split the 27 points) as a plain loop over an int.
 template <int ELEM, class Fn>
-__device__ __forceinline__ void for_points(Fn &&fn)
+__device__ __forceinline__ void for_points(int part, Fn &&fn)
 {
     if constexpr (ELEM == kQ27) {
+        constexpr int LPE = lanes_per_elem(kQ27), NT = (ElemDef<kQ27>::nq + LPE - 1) / LPE;
 #pragma nounroll
-        for (int q = 0; q < ElemDef<kQ27>::nq; ++q) fn(q);
+        for (int t = 0; t < NT; ++t) {
+            const int q = part + LPE * t;
+            if (q < ElemDef<kQ27>::nq) fn(q);
+        }
     } else {
         point_loop<ElemDef<ELEM>::nq>(fn);
     }
 }
 
-// Q27 per-point tables: for parent coordinate index p (the Gauss point
-// -sqrt(3/5), 0, +sqrt(3/5)) the 1-D values L_0..L_2 and derivatives
-// L_0'..L_2'; and the 27 point weights in point order.
-struct Q27Tab {
-    double v[3][6];
-    double w[27];
-};
-static __constant__ Q27Tab kQ27Tab = {
-    {{ElemDef<kQ27>::lag1(0, -ElemDef<kQ27>::g), ElemDef<kQ27>::lag1(1, -ElemDef<kQ27>::g),
-      ElemDef<kQ27>::lag1(2, -ElemDef<kQ27>::g), ElemDef<kQ27>::dlag1(0, -ElemDef<kQ27>::g),
-      ElemDef<kQ27>::dlag1(1, -ElemDef<kQ27>::g), ElemDef<kQ27>::dlag1(2, -ElemDef<kQ27>::g)},
-     {ElemDef<kQ27>::lag1(0, 0.0), ElemDef<kQ27>::lag1(1, 0.0), ElemDef<kQ27>::lag1(2, 0.0),
-      ElemDef<kQ27>::dlag1(0, 0.0), ElemDef<kQ27>::dlag1(1, 0.0), ElemDef<kQ27>::dlag1(2, 0.0)},
-     {ElemDef<kQ27>::lag1(0, ElemDef<kQ27>::g), ElemDef<kQ27>::lag1(1, ElemDef<kQ27>::g),
-      ElemDef<kQ27>::lag1(2, ElemDef<kQ27>::g), ElemDef<kQ27>::dlag1(0, ElemDef<kQ27>::g),
-      ElemDef<kQ27>::dlag1(1, ElemDef<kQ27>::g), ElemDef<kQ27>::dlag1(2, ElemDef<kQ27>::g)}},
-    {ElemDef<kQ27>::weight(0), ElemDef<kQ27>::weight(1), ElemDef<kQ27>::weight(2), ElemDef<kQ27>::weight(3),
-     ElemDef<kQ27>::weight(4), ElemDef<kQ27>::weight(5), ElemDef<kQ27>::weight(6), ElemDef<kQ27>::weight(7),
-     ElemDef<kQ27>::weight(8), ElemDef<kQ27>::weight(9), ElemDef<kQ27>::weight(10), ElemDef<kQ27>::weight(11),
-     ElemDef<kQ27>::weight(12), ElemDef<kQ27>::weight(13), ElemDef<kQ27>::weight(14), ElemDef<kQ27>::weight(15),
-     ElemDef<kQ27>::weight(16), ElemDef<kQ27>::weight(17), ElemDef<kQ27>::weight(18), ElemDef<kQ27>::weight(19),
-     ElemDef<kQ27>::weight(20), ElemDef<kQ27>::weight(21), ElemDef<kQ27>::weight(22), ElemDef<kQ27>::weight(23),
-     ElemDef<kQ27>::weight(24), ElemDef<kQ27>::weight(25), ElemDef<kQ27>::weight(26)}};
-
 // 1-D values of the three directions at Q27 point q (L: values, D:
-// derivatives; [direction][node index along it]).
+// derivatives; [direction][node index along it]), from the Gauss
+// coordinate of each direction.  The two lanes of an element evaluate
+// different points, so these are per-lane values.
 struct Q27Pt {
     double L[3][3], D[3][3];
 };
 __device__ __forceinline__ Q27Pt q27_point(int q)
 {
+    using E = ElemDef<kQ27>;
     Q27Pt t;
     const int p[3] = {q % 3, (q / 3) % 3, q / 9};
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
+        const double s = p[d] == 0 ? -E::g : (p[d] == 1 ? 0.0 : E::g);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            t.L[d][i] = kQ27Tab.v[p[d]][i];
-            t.D[d][i] = kQ27Tab.v[p[d]][3 + i];
+            t.L[d][i] = E::lag1(i, s);
+            t.D[d][i] = E::dlag1(i, s);
         }
+    }
     return t;
 }
 
@@ -113,7 +98,7 @@ __device__ __forceinline__ Q27Pt q27_point(int q)
 template <int ELEM, class QT>
 __device__ __forceinline__ double weight_at(QT q)
 {
-    if constexpr (ELEM == kQ27) return kQ27Tab.w[(int)q];
+    if constexpr (ELEM == kQ27) return ElemDef<kQ27>::weight((int)q);
     else return ElemDef<ELEM>::weight(QT::value);
 }
 
@@ -752,11 +737,11 @@ struct Rec {
 // Forward: fe[a] = sum_q w_q J_p P(F_q, Fdot_q) h_a   (Sec. 4.3 with Sec. 6)
 template <int ELEM, int LAW, bool DAMPED, int MODE, int NEN>
 __device__ __forceinline__ void fwd_element(const double *sm, const int (&na)[NEN], const Mat &mt,
-                                            double (&fe)[NEN][3])
+                                            double (&fe)[NEN][3], int part)
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpFwd, DAMPED, MODE>;
-    for_points<ELEM>([&](auto q) {
+    for_points<ELEM>(part, [&](auto q) {
         qp_fence();
         m3 K, G, F, Fd, P, Qm;
         double detJ, r;
@@ -785,7 +770,7 @@ __device__ __forceinline__ void fwd_element(const double *sm, const int (&na)[NE
 // SIMD.
 template <int ELEM, int LAW, bool DAMPED, bool WANT_GT, int NEN>
 __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NEN], const Mat &mt,
-                                            double (&gx)[NEN][3], double (&gv)[NEN][3], double (&gt)[5])
+                                            double (&gx)[NEN][3], double (&gv)[NEN][3], double (&gt)[5], int part)
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpVjp, DAMPED>;
@@ -794,7 +779,7 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
     // first node there.  The H8 adjoint keeps tile-relative positions (with
     // them its schedule spills hundreds of registers).
     constexpr bool REL = WANT_GT && ELEM == kT10;
-    for_points<ELEM>([&](auto q) {
+    for_points<ELEM>(part, [&](auto q) {
         m3 K, G, F, Gw, Fb;
         double detJ, r;
         ref_geometry<ELEM, NEN, REL>(q, sm + R::oX, na, K, detJ, r);
@@ -873,11 +858,11 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
 //   df_a += c_q dP h_a.
 template <int ELEM, int LAW, bool DAMPED, bool DT, int NEN>
 __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NEN], const Mat &mt, const Mat &dmt,
-                                            double (&df)[NEN][3])
+                                            double (&df)[NEN][3], int part)
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpJvp, DAMPED>;
-    for_points<ELEM>([&](auto q) {
+    for_points<ELEM>(part, [&](auto q) {
         qp_fence();
         m3 K, G, F, dF, dP;
         double detJ, r;
@@ -951,13 +936,13 @@ __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NE
 // field of the node records.
 template <int ELEM, int NEN>
 __device__ __forceinline__ void mass_element(const double *su, const int (&na)[NEN], const double *coef,
-                                             int64_t stride, double scale, double (&fe)[NEN][3])
+                                             int64_t stride, double scale, double (&fe)[NEN][3], int part = 0)
 {
     if constexpr (ELEM == kQ27) {
         // the stiffness rule; s_ijk = L_i L_j L_k, contracted one direction
         // at a time in both products
 #pragma nounroll
-        for (int q = 0; q < 27; ++q) {
+        for (int q = part; q < 27; q += lanes_per_elem(kQ27)) {
             qp_fence();
             const Q27Pt t = q27_point(q);
             double u[3] = {0.0, 0.0, 0.0};
@@ -1169,7 +1154,7 @@ __device__ __forceinline__ TileCsr csr_layout(double *smem, int nl, int rec_len,
 // tables are read once per call and loaded non-temporally.  The slot ids
 // are copied as 32-bit words; a tile's entries start at an even global
 // index (the host pads every tile's list to an even length).
-template <int NEN, int SPT = kStagePerThread>
+template <int NEN, int SPT = kStagePerThread, int LPE = 1>
 __device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, const TileDesc &t, int tid, int nthr)
 {
     const int32_t *gptr = m.lnode_ptr + t.ptr_begin;
@@ -1185,8 +1170,9 @@ __device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, co
         const int l = tid + k * nthr;
         dv[k] = l < t.n_node ? __builtin_nontemporal_load(m.lnode_dst + t.node_begin + l) : 0;
     }
-    // NEN * n_elem entries = NEN * n_elem / 2 words; at most NEN / 2 words per thread
-    constexpr int W = (NEN + 1) / 2;
+    // NEN * n_elem entries = NEN * n_elem / 2 words over te * LPE threads:
+    // at most NEN / (2 LPE) words per thread
+    constexpr int W = (NEN + 2 * LPE - 1) / (2 * LPE);
     const int n_words = (NEN * t.n_elem + 1) / 2;
     const uint32_t *gw = reinterpret_cast<const uint32_t *>(m.lnode_slot + base);
     uint32_t wv[W];
@@ -1253,39 +1239,60 @@ __device__ __forceinline__ void reduce_components(const DevMesh &m, const TileDe
 // round (the host picks NC so that NC x NEN x te slot doubles fit the
 // workgroup's LDS); the slots a * te + i overwrite the node records, which
 // are dead once every lane is done.
-template <int NEN, int NC>
+template <int NEN, int NC, int LPE>
 __device__ __forceinline__ void assemble_nc(const DevMesh &m, const TileDesc &t, const TileCsr &c,
                                             double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
                                             double *__restrict__ out, const double *__restrict__ sub, int field,
                                             int tid, int te)
 {
     const int stride = NEN * te;
+    const int ie = tid / LPE, part = tid % LPE, nthr = te * LPE;
 #pragma unroll
     for (int r0 = 0; r0 < 3; r0 += NC) {
         __syncthreads();
-        if (active) {
+        if (active && part == 0) {
 #pragma unroll
             for (int k = 0; k < NC; ++k)
                 if (r0 + k < 3) {
 #pragma unroll
-                    for (int a = 0; a < NEN; ++a) sm[k * stride + a * te + tid] = fe[a][r0 + k];
+                    for (int a = 0; a < NEN; ++a) sm[k * stride + a * te + ie] = fe[a][r0 + k];
                 }
         }
         __syncthreads();
-        if (r0 + NC <= 3) reduce_components<NC>(m, t, c, sm, stride, out, sub, field, r0, tid, te);
-        else reduce_components<(3 % NC) ? (3 % NC) : 1>(m, t, c, sm, stride, out, sub, field, r0, tid, te);
+        if (r0 + NC <= 3) reduce_components<NC>(m, t, c, sm, stride, out, sub, field, r0, tid, nthr);
+        else reduce_components<(3 % NC) ? (3 % NC) : 1>(m, t, c, sm, stride, out, sub, field, r0, tid, nthr);
     }
 }
 
-template <int NEN>
+// LPE lanes per element (Q27: 2): every lane holds its element's whole
+// vector (the lanes' sums, see lane_sum) and the first lane of each element
+// writes its slots.
+template <int NEN, int LPE = 1>
 __device__ __forceinline__ void assemble(const DevMesh &m, const TileDesc &t, const TileCsr &c,
                                          double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
                                          double *__restrict__ out, int field, int tid, int te, int nc,
                                          const double *__restrict__ sub = nullptr)
 {
-    if (nc >= 3) assemble_nc<NEN, 3>(m, t, c, sm, fe, active, out, sub, field, tid, te);
-    else if (nc == 2) assemble_nc<NEN, 2>(m, t, c, sm, fe, active, out, sub, field, tid, te);
-    else assemble_nc<NEN, 1>(m, t, c, sm, fe, active, out, sub, field, tid, te);
+    if (nc >= 3) assemble_nc<NEN, 3, LPE>(m, t, c, sm, fe, active, out, sub, field, tid, te);
+    else if (nc == 2) assemble_nc<NEN, 2, LPE>(m, t, c, sm, fe, active, out, sub, field, tid, te);
+    else assemble_nc<NEN, 1, LPE>(m, t, c, sm, fe, active, out, sub, field, tid, te);
+}
+
+// Sum of the partial element vectors of an element's LPE lanes (neighbours
+// in the wavefront), left in every one of them: a butterfly over lane
+// distances 1, 2, ..., whose additions give the same value in every lane
+// (x + y and y + x are the same number).  Run by every lane.
+template <int LPE, int N>
+__device__ __forceinline__ void lane_sum(double (&v)[N][3])
+{
+    if constexpr (LPE > 1) {
+#pragma unroll
+        for (int off = 1; off < LPE; off <<= 1)
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int r = 0; r < 3; ++r) v[a][r] += __shfl_xor(v[a][r], off, 64);
+    }
 }
 
 // Zeros for every destination of the tile's nodes (an undamped tile's share
@@ -1317,35 +1324,37 @@ template <int ELEM, int LAW, bool DAMPED, int MODE>
 __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpFwd, ELEM, LAW, DAMPED, MODE)))) void k_fwd(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
+    constexpr int LPE = lanes_per_elem(ELEM);
     using R = Rec<kOpFwd, DAMPED, MODE>;
     extern __shared__ double smem[];
     const int ti = xcd_tile(blockIdx.x, ntile);
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, ie = tid / LPE, part = tid % LPE, nthr = te * LPE;
     // staging issues long-latency loads: its waves go first while other
     // tiles on the compute unit compute
     __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
-    stage_csr<NEN, stage_per_thread(ELEM)>(csr, m, t, tid, te);
-    stage_tile<kOpFwd, DAMPED, MODE, true, stage_per_thread(ELEM)>(smem, m, c, t, tid, te);
+    stage_csr<NEN, stage_per_thread(ELEM), LPE>(csr, m, t, tid, nthr);
+    stage_tile<kOpFwd, DAMPED, MODE, true, stage_per_thread(ELEM)>(smem, m, c, t, tid, nthr);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double fe[NEN][3];
 #pragma unroll
     for (int a = 0; a < NEN; ++a) fe[a][0] = fe[a][1] = fe[a][2] = 0.0;
-    const bool active = tid < t.n_elem;
+    const bool active = ie < t.n_elem;
     if (active) {
         int na[NEN];
-        load_na<NEN, R::len>(m, t, tid, te, na);
-        const int uid = m.elem_uid[t.elem_begin + tid];
+        load_na<NEN, R::len>(m, t, ie, te, na);
+        const int uid = m.elem_uid[t.elem_begin + ie];
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
-        fwd_element<ELEM, LAW, DAMPED, MODE>(smem, na, mt, fe);
+        fwd_element<ELEM, LAW, DAMPED, MODE>(smem, na, mt, fe, part);
         if constexpr (MODE == kModeStep)
             if (m.mass_c)
-                mass_element<ELEM>(smem + R::ou, na, m.mass_c + t.elem_begin + tid, m.n_elem, 1.0 / c.h, fe);
+                mass_element<ELEM>(smem + R::ou, na, m.mass_c + t.elem_begin + ie, m.n_elem, 1.0 / c.h, fe, part);
     }
-    assemble<NEN>(m, t, csr, smem, fe, active, c.out0, 0, tid, te, nc, MODE == kModeStep ? c.sub : nullptr);
+    lane_sum<LPE>(fe);
+    assemble<NEN, LPE>(m, t, csr, smem, fe, active, c.out0, 0, tid, te, nc, MODE == kModeStep ? c.sub : nullptr);
 }
 
 // Two waves per SIMD (256 registers); the damped Mooney-Rivlin adjoint, which
@@ -1355,18 +1364,19 @@ template <int ELEM, int LAW, bool DAMPED, bool WANT_GT>
 __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpVjp, ELEM, LAW, DAMPED)))) void k_vjp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
+    constexpr int LPE = lanes_per_elem(ELEM);
     using R = Rec<kOpVjp, DAMPED>;
     extern __shared__ double smem[];
     const int ti = xcd_tile(blockIdx.x, ntile);
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, ie = tid / LPE, part = tid % LPE, nthr = te * LPE;
     // staging issues long-latency loads: its waves go first while other
     // tiles on the compute unit compute
     __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
-    stage_csr<NEN, stage_per_thread(ELEM)>(csr, m, t, tid, te);
-    stage_tile<kOpVjp, DAMPED, kModePlain, WANT_GT && ELEM == kT10, stage_per_thread(ELEM)>(smem, m, c, t, tid, te);
+    stage_csr<NEN, stage_per_thread(ELEM), LPE>(csr, m, t, tid, nthr);
+    stage_tile<kOpVjp, DAMPED, kModePlain, WANT_GT && ELEM == kT10, stage_per_thread(ELEM)>(smem, m, c, t, tid, nthr);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double gx[NEN][3], gv[NEN][3], gt[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1374,26 +1384,35 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     for (int a = 0; a < NEN; ++a)
 #pragma unroll
         for (int r = 0; r < 3; ++r) gx[a][r] = gv[a][r] = 0.0;
-    const bool active = tid < t.n_elem;
+    const bool active = ie < t.n_elem;
+    int uid = 0;
     if (active) {
         int na[NEN];
-        load_na<NEN, R::len>(m, t, tid, te, na);
-        const int uid = m.elem_uid[t.elem_begin + tid];
+        load_na<NEN, R::len>(m, t, ie, te, na);
+        uid = m.elem_uid[t.elem_begin + ie];
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
-        vjp_element<ELEM, LAW, DAMPED, WANT_GT>(smem, na, mt, gx, gv, gt);
-        if (WANT_GT) {
-            // rows a law does not use (and the viscous rows when undamped) are 0
-            c.gtheta[uid] = gt[0];
-            c.gtheta[m.n_elem + uid] = (LAW == 1 || LAW == 0) ? gt[1] : 0.0;
-            c.gtheta[2 * m.n_elem + uid] = LAW == 0 ? 0.0 : gt[2];
-            c.gtheta[3 * m.n_elem + uid] = DAMPED ? gt[3] : 0.0;
-            c.gtheta[4 * m.n_elem + uid] = DAMPED ? gt[4] : 0.0;
-        }
+        vjp_element<ELEM, LAW, DAMPED, WANT_GT>(smem, na, mt, gx, gv, gt, part);
     }
-    if (c.out0) assemble<NEN>(m, t, csr, smem, gx, active, c.out0, 0, tid, te, nc);
+    lane_sum<LPE>(gx);
+    if constexpr (DAMPED) lane_sum<LPE>(gv);
+    if constexpr (WANT_GT && LPE > 1) {
+#pragma unroll
+        for (int off = 1; off < LPE; off <<= 1)
+#pragma unroll
+            for (int r = 0; r < 5; ++r) gt[r] += __shfl_xor(gt[r], off, 64);
+    }
+    if (WANT_GT && active && part == 0) {
+        // rows a law does not use (and the viscous rows when undamped) are 0
+        c.gtheta[uid] = gt[0];
+        c.gtheta[m.n_elem + uid] = (LAW == 1 || LAW == 0) ? gt[1] : 0.0;
+        c.gtheta[2 * m.n_elem + uid] = LAW == 0 ? 0.0 : gt[2];
+        c.gtheta[3 * m.n_elem + uid] = DAMPED ? gt[3] : 0.0;
+        c.gtheta[4 * m.n_elem + uid] = DAMPED ? gt[4] : 0.0;
+    }
+    if (c.out0) assemble<NEN, LPE>(m, t, csr, smem, gx, active, c.out0, 0, tid, te, nc);
     if (c.out1) {
-        if constexpr (DAMPED) assemble<NEN>(m, t, csr, smem, gv, active, c.out1, 1, tid, te, nc);
-        else zero_nodes(m, t, csr, c.out1, 1, tid, te);
+        if constexpr (DAMPED) assemble<NEN, LPE>(m, t, csr, smem, gv, active, c.out1, 1, tid, te, nc);
+        else zero_nodes(m, t, csr, c.out1, 1, tid, nthr);
     }
 }
 
@@ -1409,37 +1428,40 @@ template <int ELEM, int LAW, bool DAMPED, bool DT, int MODE>
 __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(waves_per_simd(kOpJvp, ELEM, LAW, DAMPED, MODE)))) void k_jvp(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
+    constexpr int LPE = lanes_per_elem(ELEM);
     using R = Rec<kOpJvp, DAMPED, MODE>;
     extern __shared__ double smem[];
     const int ti = xcd_tile(blockIdx.x, ntile);
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, ie = tid / LPE, part = tid % LPE, nthr = te * LPE;
     // staging issues long-latency loads: its waves go first while other
     // tiles on the compute unit compute
     __builtin_amdgcn_s_setprio(3);
     const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
-    stage_csr<NEN, stage_per_thread(ELEM)>(csr, m, t, tid, te);
-    stage_tile<kOpJvp, DAMPED, MODE, false, stage_per_thread(ELEM)>(smem, m, c, t, tid, te);
+    stage_csr<NEN, stage_per_thread(ELEM), LPE>(csr, m, t, tid, nthr);
+    stage_tile<kOpJvp, DAMPED, MODE, false, stage_per_thread(ELEM)>(smem, m, c, t, tid, nthr);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double df[NEN][3];
 #pragma unroll
     for (int a = 0; a < NEN; ++a) df[a][0] = df[a][1] = df[a][2] = 0.0;
-    const bool active = tid < t.n_elem;
+    const bool active = ie < t.n_elem;
     if (active) {
         int na[NEN];
-        load_na<NEN, R::len>(m, t, tid, te, na);
-        const int uid = m.elem_uid[t.elem_begin + tid];
+        load_na<NEN, R::len>(m, t, ie, te, na);
+        const int uid = m.elem_uid[t.elem_begin + ie];
         const Mat mt = load_mat<LAW>(m.blocks[t.block], c.theta, m.n_elem, uid, DAMPED);
         Mat dmt{};
         if constexpr (DT) dmt = load_mat<LAW>(m.blocks[t.block], c.dtheta, m.n_elem, uid, DAMPED);
-        jvp_element<ELEM, LAW, DAMPED, DT>(smem, na, mt, dmt, df);
+        jvp_element<ELEM, LAW, DAMPED, DT>(smem, na, mt, dmt, df, part);
         if constexpr (MODE == kModeStep)
             if (m.mass_c)
-                mass_element<ELEM>(smem + R::o2, na, m.mass_c + t.elem_begin + tid, m.n_elem, 1.0 / (c.h * c.h), df);
+                mass_element<ELEM>(smem + R::o2, na, m.mass_c + t.elem_begin + ie, m.n_elem, 1.0 / (c.h * c.h), df,
+                                   part);
     }
-    assemble<NEN>(m, t, csr, smem, df, active, c.out0, 0, tid, te, nc);
+    lane_sum<LPE>(df);
+    assemble<NEN, LPE>(m, t, csr, smem, df, active, c.out0, 0, tid, te, nc);
 }
 
 // Consistent-mass action y = M u (Sec. 4.1): the tile stages u only.
@@ -1447,15 +1469,16 @@ template <int ELEM>
 __global__ __launch_bounds__(TLFEA_MAX_TE) void k_mass(DevMesh m, CallArgs c, int tile0, int ntile, int te, int nl, int nc)
 {
     constexpr int NEN = ElemDef<ELEM>::nen;
+    constexpr int LPE = lanes_per_elem(ELEM);
     constexpr int LEN = record_len(kOpMass, false);
     extern __shared__ double smem[];
     const int ti = xcd_tile(blockIdx.x, ntile);
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, ie = tid / LPE, part = tid % LPE, nthr = te * LPE;
     const TileCsr csr = csr_layout(smem, nl, LEN, NEN, te, nc);
     constexpr int SPT = stage_per_thread(ELEM);
-    stage_csr<NEN, SPT>(csr, m, t, tid, te);
+    stage_csr<NEN, SPT, LPE>(csr, m, t, tid, nthr);
     {
         const int32_t *gid = m.lnode_gid + t.node_begin;
         const uint16_t *lpos = m.lnode_pos + t.node_begin;
@@ -1463,7 +1486,7 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_mass(DevMesh m, CallArgs c, in
         double v[SPT][3];
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
-            const int l = tid + k * te;
+            const int l = tid + k * nthr;
             g[k] = l < t.n_node ? __builtin_nontemporal_load(gid + l) : -1;
             p[k] = l < t.n_node ? (int)__builtin_nontemporal_load(lpos + l) : 0;
         }
@@ -1481,13 +1504,14 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_mass(DevMesh m, CallArgs c, in
     double fe[NEN][3];
 #pragma unroll
     for (int a = 0; a < NEN; ++a) fe[a][0] = fe[a][1] = fe[a][2] = 0.0;
-    const bool active = tid < t.n_elem;
+    const bool active = ie < t.n_elem;
     if (active && m.mass_c) {
         int na[NEN];
-        load_na<NEN, LEN>(m, t, tid, te, na);
-        mass_element<ELEM>(smem, na, m.mass_c + t.elem_begin + tid, m.n_elem, 1.0, fe);
+        load_na<NEN, LEN>(m, t, ie, te, na);
+        mass_element<ELEM>(smem, na, m.mass_c + t.elem_begin + ie, m.n_elem, 1.0, fe, part);
     }
-    assemble<NEN>(m, t, csr, smem, fe, active, c.out0, 0, tid, te, nc);
+    lane_sum<LPE>(fe);
+    assemble<NEN, LPE>(m, t, csr, smem, fe, active, c.out0, 0, tid, te, nc);
 }
 
 // Quadrature points with det F <= 0 (inverted or collapsed there).  The
@@ -1507,14 +1531,15 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_inverted(DevMesh m, CallArgs c
     const int ti = xcd_tile(blockIdx.x, ntile);
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
-    const int tid = threadIdx.x;
-    stage_tile<kOpFwd, false, kModePlain, true, stage_per_thread(ELEM)>(smem, m, c, t, tid, te);
+    constexpr int LPE = lanes_per_elem(ELEM);
+    const int tid = threadIdx.x, ie = tid / LPE, part = tid % LPE;
+    stage_tile<kOpFwd, false, kModePlain, true, stage_per_thread(ELEM)>(smem, m, c, t, tid, te * LPE);
     __syncthreads();
     int n = 0;
-    if (tid < t.n_elem) {
+    if (ie < t.n_elem) {
         int na[NEN];
-        load_na<NEN, R::len>(m, t, tid, te, na);
-        for_points<ELEM>([&](auto q) {
+        load_na<NEN, R::len>(m, t, ie, te, na);
+        for_points<ELEM>(part, [&](auto q) {
             m3 K, G, F, cof;
             double detJ, r;
             ref_geometry<ELEM, NEN, true>(q, smem + R::oX, na, K, detJ, r);
@@ -1534,9 +1559,10 @@ hipError_t launch_inverted_class(int te, int n_tiles, size_t lds, hipStream_t s,
                                  const CallArgs &c, int tile0, unsigned long long *count)
 {
     if (n_tiles <= 0) return hipSuccess;
-    if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
+    const int nthr = te * lanes_per_elem(ELEM);
+    if (te <= 0 || nthr > TLFEA_MAX_TE || (nthr & 63)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
-    k_inverted<ELEM><<<grid, te, lds, s>>>(m, c, tile0, n_tiles, te, count);
+    k_inverted<ELEM><<<grid, nthr, lds, s>>>(m, c, tile0, n_tiles, te, count);
     return hipGetLastError();
 }
 
@@ -1544,17 +1570,18 @@ template <int OP, int ELEM, int LAW, bool DAMPED, int GT, int MODE>
 hipError_t launch_one(dim3 grid, int te, size_t lds, hipStream_t s, const DevMesh &m, const CallArgs &c, int tile0,
                       int ntile, int nl, int nc)
 {
-    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED, MODE><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+    const int nthr = te * lanes_per_elem(ELEM);
+    if constexpr (OP == kOpFwd) k_fwd<ELEM, LAW, DAMPED, MODE><<<grid, nthr, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     else if constexpr (OP == kOpVjp) {
         // one adjoint translation unit per gtheta choice (each with the
         // instruction scheduler that suits it); the host picks the unit
         if ((c.gtheta != nullptr) != (GT != 0)) return hipErrorInvalidValue;
-        k_vjp<ELEM, LAW, DAMPED, GT != 0><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+        k_vjp<ELEM, LAW, DAMPED, GT != 0><<<grid, nthr, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     } else if constexpr (MODE == kModeStep) {
-        k_jvp<ELEM, LAW, DAMPED, false, kModeStep><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+        k_jvp<ELEM, LAW, DAMPED, false, kModeStep><<<grid, nthr, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     } else {
-        if (c.dtheta) k_jvp<ELEM, LAW, DAMPED, true, kModePlain><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
-        else k_jvp<ELEM, LAW, DAMPED, false, kModePlain><<<grid, te, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+        if (c.dtheta) k_jvp<ELEM, LAW, DAMPED, true, kModePlain><<<grid, nthr, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
+        else k_jvp<ELEM, LAW, DAMPED, false, kModePlain><<<grid, nthr, lds, s>>>(m, c, tile0, ntile, te, nl, nc);
     }
     return hipGetLastError();
 }
@@ -1568,7 +1595,8 @@ hipError_t launch_class(int law, int damped, int te, int n_tiles, size_t lds, hi
                         const CallArgs &c, int tile0, int nl, int nc)
 {
     if (n_tiles <= 0) return hipSuccess;
-    if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
+    const int nthr = te * lanes_per_elem(ELEM);
+    if (te <= 0 || nthr > TLFEA_MAX_TE || (nthr & 63)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
     switch (law * 2 + (damped ? 1 : 0)) {
     case 0: return launch_one<OP, ELEM, 0, false, GT, MODE>(grid, te, lds, s, m, c, tile0, n_tiles, nl, nc);
@@ -1586,9 +1614,10 @@ hipError_t launch_mass_class(int te, int n_tiles, size_t lds, hipStream_t s, con
                              int tile0, int nl, int nc)
 {
     if (n_tiles <= 0) return hipSuccess;
-    if (te <= 0 || te > TLFEA_MAX_TE || (te & 63)) return hipErrorInvalidValue;
+    const int nthr = te * lanes_per_elem(ELEM);
+    if (te <= 0 || nthr > TLFEA_MAX_TE || (nthr & 63)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
-    k_mass<ELEM><<<grid, te, lds, s>>>(m, c, tile0, n_tiles, te, nl, nc);
+    k_mass<ELEM><<<grid, nthr, lds, s>>>(m, c, tile0, n_tiles, te, nl, nc);
     return hipGetLastError();
 }
 

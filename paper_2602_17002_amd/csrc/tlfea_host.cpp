@@ -396,9 +396,11 @@ static int default_te(int elem) { return elem == kQ27 ? 64 : 256; }
 // least two.
 static int64_t lds_budget(int kind, int elem, int law, int damped, int te, int64_t lds_dev)
 {
-    // Q27 tiles hold about 11 nodes per element: two 64-element tiles (one
-    // wave each) per compute unit
-    if (elem == kQ27) return std::min<int64_t>(lds_dev, 163840 / std::max(1, 128 / te));
+    // Q27 tiles hold about 11 nodes per element and run at one wave per
+    // SIMD: as many tiles per compute unit as its four waves hold (two of 64
+    // elements, two lanes each)
+    if (elem == kQ27)
+        return std::min<int64_t>(lds_dev, 163840 / std::max(1, 256 / (te * lanes_per_elem(kQ27))));
     const int op = kind_op(kind), mode = kind_mode(kind);
     const int64_t waves_per_cu =
         kind == kKFwd ? 12 : (kind == kKMass ? 16 : 4 * std::max(2, waves_per_simd(op, elem, law, damped != 0, mode)));
@@ -411,7 +413,7 @@ static int kind_record_len(int kind, bool damped) { return record_len(kind_op(ki
 static int nl_limit(int elem, int law, int te, int damped, int64_t lds_dev)
 {
     const int nen = nen_of(elem);
-    int64_t nl = (int64_t)stage_per_thread(elem) * te;
+    int64_t nl = (int64_t)stage_per_thread(elem) * te * lanes_per_elem(elem);
     // full 256-element tiles: at most 600 nodes even where the LDS would hold
     // more.  Compact T10 tiles have about 550 (p99 670 without the cap), and
     // letting the ragged ones grow further made the undamped forward 8 %
@@ -457,7 +459,10 @@ static int comps_per_round(const ClassRange &c, int kind, int64_t lds_dev)
 // connectivity (local = index in the sorted node list); returns pos[local].
 static void place_records(const uint16_t *conn, int n_elem, int n_node, int elem, int te, std::vector<uint16_t> &pos)
 {
-    constexpr int kGroup = 16, kPairs = 16;
+    // a 16-lane group holds 16 / lanes_per_elem elements (the lanes of one
+    // element read the same node address together)
+    constexpr int kPairs = 16;
+    const int kGroup = 16 / lanes_per_elem(elem);
     const int nen = nen_of(elem), nq = nq_of(elem);
     std::vector<int> reads(nen, 0);
     for (int a = 0; a < nen; ++a)
@@ -639,7 +644,7 @@ static void grow_tiles(const tlfea_block &B, int64_t n_nodes, const double *X, c
 // element in Morton order among equals).
 static void order_lanes(const tlfea_block &B, const std::vector<int64_t> &ord, std::vector<int64_t> &grp)
 {
-    constexpr int kGroup = 16;
+    const int kGroup = 16 / lanes_per_elem(B.elem);
     const int nen = nen_of(B.elem);
     std::sort(grp.begin(), grp.end());
     const int ng = (int)grp.size();
@@ -770,7 +775,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                 t.conn_begin = (int32_t)hb.conn_local.size();
                 t.block = b;
                 t.ref = 0;
-                if (t.n_node > nlmax || t.n_node > stage_per_thread(B.elem) * te)
+                if (t.n_node > nlmax || t.n_node > stage_per_thread(B.elem) * te * lanes_per_elem(B.elem))
                     return fail(TLFEA_E_UNSUPPORTED, "tile with %d nodes exceeds the limit %d", t.n_node, nlmax);
                 for (size_t l = 0; l < nodes.size(); ++l) {
                     local[nodes[l]] = (int32_t)l;

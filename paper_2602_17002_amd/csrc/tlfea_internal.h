@@ -19,14 +19,20 @@ struct TileDesc {
                           // (the tile's node nearest the centroid of its nodes)
 };
 
+// Lanes per element: a T10 or H8 element is one lane's work; a Q27 element
+// (element type 2) is split over two neighbouring lanes, each evaluating
+// every other quadrature point, so that a tile of te elements runs te x 2
+// threads (the LDS of its node records allows few tiles per compute unit).
+constexpr int lanes_per_elem(int elem) { return elem == 2 ? 2 : 1; }
+
 // Node records a thread stages at most: a tile holds at most this many
 // nodes per thread of its workgroup (element types 0, 1: T10, H8, about
 // 2.2 and 1.6 distinct nodes per element in a compact tile; 2: Q27, about
-// 11).  The staging loads are issued in rounds of at most kStageRound nodes
-// per thread.
+// 11 per element, 6 per thread).  The staging loads are issued in rounds of
+// at most kStageRound nodes per thread.
 constexpr int kStagePerThread = 3;
 constexpr int kStageRound = 6;
-constexpr int stage_per_thread(int elem) { return elem == 2 ? 12 : kStagePerThread; }
+constexpr int stage_per_thread(int elem) { return elem == 2 ? 6 : kStagePerThread; }
 
 struct BlockDesc {
     double theta[5];

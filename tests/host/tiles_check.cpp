@@ -131,7 +131,7 @@ int main(int argc, char **argv)
         const TileDesc &t = hb.tiles[ti];
         const int b = t.block, nen = nen_of(blocks[b].elem), T = te[b];
         CHECK(t.n_elem >= 1 && t.n_elem <= T, "tile %zu has %d elements (te %d)", ti, t.n_elem, T);
-        CHECK(t.n_node <= stage_per_thread(blocks[b].elem) * T, "tile %zu has %d nodes", ti, t.n_node);
+        CHECK(t.n_node <= stage_per_thread(blocks[b].elem) * T * lanes_per_elem(blocks[b].elem), "tile %zu has %d nodes", ti, t.n_node);
         // sorted unique node ids, positions a permutation
         std::vector<int> pos_seen(t.n_node, 0), local_of_pos(t.n_node, -1);
         for (int l = 0; l < t.n_node; ++l) {
