@@ -468,6 +468,28 @@ def batched_vs_plain(steps, warmup):
         for name, fn in (("batched", run_batched), ("plain", run_plain), ("plain_graph", g_plain.replay)):
             res[name] = timed(fn, steps, warmup, s)[0]
         same = all(torch.equal(f_b[:, n0:n1], ff) for (_, n0, n1), ff in zip(plains, fs))
+
+        # forward + backward through the autograd Function on the batched
+        # mesh: fresh output tensors every iteration (new operand pointers,
+        # so cached graphs are updated in place), against the same two calls
+        # into preallocated outputs (cached graphs replayed)
+        from paper_2602_17002_amd import TLInternalForce
+        w = torch.from_numpy(np.random.default_rng(5).standard_normal(p.x.shape)).to(dev)
+        gx_b = torch.empty_like(x)
+
+        def run_autograd():
+            xr = x.detach().requires_grad_(True)
+            f = TLInternalForce.apply(xr, None, None, batched)
+            f.backward(w)
+
+        def run_direct():
+            batched.internal_force(x, out=f_b)
+            batched.vjp(x, None, w, want_v=False, want_theta=False, out=(gx_b, None, None))
+
+        info0 = batched.info()
+        res["autograd"] = timed(run_autograd, steps, warmup, s)[0]
+        info1 = batched.info()
+        res["direct"] = timed(run_direct, steps, warmup, s)[0]
     return {"workload": f"C3: {len(p.blocks)} bodies of 200-50,000 elements, mixed T10/H8, SVK/NH, "
                         f"{p.n_elem} elements, forward f_int",
             "ms_batched": round(res["batched"], 4), "ms_plain": round(res["plain"], 4),
@@ -475,7 +497,10 @@ def batched_vs_plain(steps, warmup):
             "speedup": round(res["plain"] / res["batched"], 3),
             "speedup_vs_plain_graph": round(res["plain_graph"] / res["batched"], 3),
             "quad_pts_per_s_batched": p.n_qp / (res["batched"] * 1e-3),
-            "bitwise_equal_per_body": bool(same)}
+            "bitwise_equal_per_body": bool(same),
+            "autograd_fwd_bwd": {"ms": round(res["autograd"], 4), "ms_direct_calls": round(res["direct"], 4),
+                                 "graphs_built": info1["graphs_built"] - info0["graphs_built"],
+                                 "graphs_updated": info1["graphs_updated"] - info0["graphs_updated"]}}
 
 
 def batched_c5(steps, warmup):

@@ -42,8 +42,11 @@
  * - A TLFEA_BATCHED mesh records each call's launches (one per tile class,
  *   then the shared-node sum) into a hipGraph the first time it sees that
  *   operation with those operand pointers on that stream, and replays it
- *   afterwards; it keeps the eight most recently used graphs and waits for an
- *   evicted graph's last launch before freeing it.  On the null stream, or
+ *   afterwards.  It keeps eight graphs.  With all eight in use, new operand
+ *   pointers update the least recently used graph of the same operation and
+ *   stream in place, after that graph's last launch has finished (only the
+ *   kernel arguments differ); otherwise the least recently used graph is
+ *   evicted, again after its last launch.  On the null stream, or
  *   on a stream the caller is capturing, the launches are issued directly
  *   (the caller's graph then holds them).
  * - Every function returns a tlfea_status; nothing throws.  On a non-OK
@@ -130,6 +133,8 @@ typedef struct {
     int32_t tile_elems_t10, tile_elems_h8;   /* chosen (autotuned) tile sizes  */
     int32_t tile_elems_q27, reserved;
     int64_t device_bytes;                    /* device memory the mesh holds   */
+    int64_t graphs_built, graphs_updated;    /* TLFEA_BATCHED: graphs instantiated,
+                                                and cached ones updated in place */
 } tlfea_mesh_info;
 
 /*

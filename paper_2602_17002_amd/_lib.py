@@ -43,7 +43,7 @@ class MeshInfo(C.Structure):
                 ("n_blocks", C.c_int32), ("flags", C.c_int32),
                 ("tile_elems_t10", C.c_int32), ("tile_elems_h8", C.c_int32),
                 ("tile_elems_q27", C.c_int32), ("reserved", C.c_int32),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("graphs_built", C.c_int64), ("graphs_updated", C.c_int64)]
 
 
 class KrylovOpts(C.Structure):

@@ -237,6 +237,7 @@ struct tlfea_mesh {
     // graph cache
     std::vector<GraphEntry> graphs;
     uint64_t stamp = 0;
+    int64_t graph_builds = 0, graph_updates = 0;   // instantiated, updated in place
     bool any_damped = false;
     bool has_mass = false;     // some block has a density: mass coefficients are on the device
 };
@@ -1224,8 +1225,8 @@ static tlfea_status run(tlfea_mesh *m, int kind, const CallArgs &c, void *stream
     GraphEntry *hit = nullptr;
     for (auto &g : m->graphs)
         if (g.kind == kind && g.stream == s && std::memcmp(g.key, key, sizeof key) == 0) hit = &g;
+    hipGraph_t graph = nullptr;
     if (!hit) {
-        hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         tlfea_status st = enqueue(m, m->dm, kind, c, s, false);
         hipError_t ec = hipStreamEndCapture(s, &graph);
@@ -1234,6 +1235,35 @@ static tlfea_status run(tlfea_mesh *m, int kind, const CallArgs &c, void *stream
             return st;
         }
         if (ec != hipSuccess) return fail(TLFEA_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        // A full cache: the least recently used graph of the same operation
+        // on the same stream has the same launches with other operands, so
+        // its executable graph is updated in place (after its last launch
+        // has finished) instead of instantiating another one.
+        if (m->graphs.size() >= 8) {
+            GraphEntry *same = nullptr;
+            for (auto &g : m->graphs)
+                if (g.kind == kind && g.stream == s && (!same || g.stamp < same->stamp)) same = &g;
+            if (same) {
+                hipError_t ew = hipEventSynchronize(same->done);
+                if (ew != hipSuccess) {
+                    (void)hipGraphDestroy(graph);
+                    return fail(TLFEA_E_DEVICE, "waiting for a cached graph: %s", hipGetErrorString(ew));
+                }
+                hipGraphNode_t err_node = nullptr;
+                hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+                const hipError_t eu = hipGraphExecUpdate(same->exec, graph, &err_node, &res);
+                if (eu == hipSuccess && res == hipGraphExecUpdateSuccess) {
+                    (void)hipGraphDestroy(graph);
+                    std::memcpy(same->key, key, sizeof key);
+                    ++m->graph_updates;
+                    hit = same;
+                } else {
+                    (void)hipGetLastError();   // a refused update leaves no sticky error
+                }
+            }
+        }
+    }
+    if (!hit) {
         GraphEntry ge;
         ge.kind = kind;
         std::memcpy(ge.key, key, sizeof key);
@@ -1242,6 +1272,7 @@ static tlfea_status run(tlfea_mesh *m, int kind, const CallArgs &c, void *stream
         hipError_t ei = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (ei != hipSuccess) return fail(TLFEA_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        ++m->graph_builds;
         ei = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming);
         if (ei != hipSuccess) {
             (void)hipGraphExecDestroy(ge.exec);
@@ -1793,6 +1824,8 @@ extern "C" tlfea_status tlfea_get_mesh_info(const tlfea_mesh *m, tlfea_mesh_info
     info->tile_elems_q27 = m->te_q27;
     info->reserved = 0;
     info->device_bytes = m->device_bytes;
+    info->graphs_built = m->graph_builds;
+    info->graphs_updated = m->graph_updates;
     return TLFEA_OK;
 }
 

@@ -383,8 +383,9 @@ def test_batched_graph_cache_eviction():
     # A batched mesh keeps one graph per (operation, operand pointers,
     # stream), at most eight, evicting the least recently used one after its
     # last launch has finished.  Twelve output buffers, cycled twice on one
-    # stream without synchronising, force evictions while earlier graphs may
-    # still run; every output must equal the plain mesh's bitwise.
+    # stream without synchronising, force in-place updates of cached graphs
+    # while earlier launches may still run; every output must equal the plain
+    # mesh's bitwise.
     import torch
     from paper_2602_17002_amd import BATCHED
     p = synth.config_multibody(6, 150, 1500, seed=9, directions=True)
@@ -407,6 +408,11 @@ def test_batched_graph_cache_eviction():
     for f, g in zip(fs, gs):
         assert np.array_equal(to_host(f), ref_f)
         assert np.array_equal(to_host(g), ref_g)
+    # with all eight graphs in use, new operand pointers update a cached
+    # graph of the same operation in place
+    info = batched.info()
+    say("graphs built", info["graphs_built"], "updated", info["graphs_updated"])
+    assert info["graphs_built"] >= 2 and info["graphs_updated"] > 0
 
 
 def test_autograd_function():
