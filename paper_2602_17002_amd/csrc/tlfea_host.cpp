@@ -2013,7 +2013,9 @@ extern "C" tlfea_status tlfea_create_joints(int64_t n_nodes, const double *X, in
         });
         tn.push_back(tnode[t]);
         for (auto &kv : e) {
-            tent.push_back(kv.first);
+            // the entry's row of the joint-major z: joint j, point p
+            const int64_t p = kv.first / std::max<int64_t>(1, nj), jj = kv.first - p * nj;
+            tent.push_back(jj * 5 + p);
             tval.push_back(kv.second);
         }
         tptr.push_back((int64_t)tent.size());

@@ -11,10 +11,11 @@ struct DevJoints {
     const int32_t *ids;       // [5][nmax][n_joints] node of each slot of each point's hosting element
     const double *sv;         // [5][nmax][n_joints] s_i(xi) of the slot (0 for unused slots)
     const double *fw;         // [4][n_joints]: f_1, f_2 (a_0.b_10, a_0.b_20), DP1 row weights w_4, w_5
-    double *z;                // [5][3][n_joints] the vector each point receives (scratch)
+    double *z;                // [n_joints][5][3] the vector each point receives (scratch;
+                              // joint-major, so an entry's three components share a line)
     const int32_t *tnode;     // [n_touched] nodes that receive joint forces
     const int64_t *tptr;      // [n_touched + 1] entry ranges
-    const int64_t *tent;      // [entries] point p and joint j of the entry: p * n_joints + j
+    const int64_t *tent;      // [entries] the entry's row of z: 5 j + p (joint j, point p)
     const double *tval;       // [entries] s_i(xi) of the entry
 };
 

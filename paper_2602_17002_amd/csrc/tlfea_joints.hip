@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_joints(DevJoints J, const double *__res
 #pragma unroll
     for (int p = 0; p < 5; ++p)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) J.z[((int64_t)p * 3 + c) * J.n_joints + j] = h * z[p][c];
+        for (int c = 0; c < 3; ++c) J.z[(j * 5 + p) * 3 + c] = h * z[p][c];
 }
 
 // out[node] (+)= sum over the node's entries of s * z[entry's point], in
@@ -88,11 +88,10 @@ __global__ __launch_bounds__(256) void k_joint_scatter(DevJoints J, double *__re
     const int64_t g = J.tnode[t];
     double s[3] = {0.0, 0.0, 0.0};
     for (int64_t k = J.tptr[t]; k < J.tptr[t + 1]; ++k) {
-        const int64_t pj = J.tent[k];                      // p * n_joints + j
-        const int64_t p = pj / J.n_joints, j = pj - p * J.n_joints;
+        const double *zr = J.z + 3 * J.tent[k];            // row 5 j + p
         const double v = J.tval[k];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) s[c] += v * J.z[(p * 3 + c) * J.n_joints + j];
+        for (int c = 0; c < 3; ++c) s[c] += v * zr[c];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

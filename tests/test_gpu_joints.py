@@ -25,6 +25,27 @@ def _random_point(rng, X, conn, elem):
     return (elem, conn[e].tolist(), xi.tolist())
 
 
+def test_joints_on_q27_hosts():
+    """Joints whose points sit in Q27 elements (27 node slots per point),
+    mixed with points in T10 elements of a second body."""
+    from paper_2602_17002_amd.joints import Joints
+    rng = np.random.default_rng(77)
+    Xa, ca = synth.box_q27(3, 3, 2, size=(0.3, 0.3, 0.2))
+    Xb, cb = synth.box_t10(3, 2, 2, size=(0.3, 0.2, 0.2), origin=(0.4, 0.0, 0.0))
+    X = np.concatenate([Xa, Xb], 1)
+    cb = cb + Xa.shape[1]
+    joints = [dict(P=_random_point(rng, X, ca, synth.Q27), Q=_random_point(rng, X, ca, synth.Q27),
+                   R=_random_point(rng, X, cb, synth.T10), S=_random_point(rng, X, cb, synth.T10),
+                   T=_random_point(rng, X, ca, synth.Q27)) for _ in range(120)]
+    q = X + rng.normal(0, 5e-4, X.shape)
+    lam = rng.normal(0, 1, (len(joints), 5))
+    say("joints on Q27", len(joints))
+    J = Joints(X, joints)
+    assert rel(to_host(J.values(to_dev(q))), O.revolute_values(X, q, joints)) <= TOL
+    g = to_host(J.scatter(to_dev(q), to_dev(lam), 2e4, 1e-3))
+    assert rel(g, O.revolute_scatter(X, q, joints, lam, 2e4, 1e-3)) <= TOL
+
+
 def _random_joints(rng, X, cb, eb, cc, ec, n):
     out = []
     for _ in range(n):
