@@ -49,7 +49,6 @@ hipError_t launch_inverted_e2_o0(int te, int n_tiles, size_t lds, hipStream_t s,
 hipError_t launch_zero_count(hipStream_t s, unsigned long long *count);
 hipError_t scratch_address(double **out);
 // vector kernels of the Newton-Krylov step (tlfea_vec.hip)
-constexpr int kDotBlocks = 256, kVecChunk = 8;
 hipError_t launch_mdot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *partial,
                        hipStream_t s);
 hipError_t launch_maxpy(const double *V, int64_t ldv, int nvec, const double *c, double *y, int64_t n, hipStream_t s);
@@ -1450,7 +1449,8 @@ extern "C" tlfea_status tlfea_newton_operator(tlfea_mesh *m, const double *q_n, 
 static int64_t newton_workspace_doubles(const tlfea_mesh *m, int restart)
 {
     const int64_t N = 3 * m->n_nodes;
-    return (int64_t)(restart + 5) * N + (int64_t)kDotBlocks * kVecChunk;
+    const int64_t chunks = (restart + 1 + kVecChunk - 1) / kVecChunk;
+    return (int64_t)(restart + 5) * N + (int64_t)kDotBlocks * kVecChunk * chunks;
 }
 
 extern "C" tlfea_status tlfea_newton_workspace(const tlfea_mesh *m, int32_t restart, int64_t *n_doubles)
@@ -1474,20 +1474,23 @@ struct Krylov {
     double *partial;
     std::vector<double> host;
 
+    // out[k] = V_k . w, k < nvec: every chunk of eight vectors writes its own
+    // partials, then one copy and one synchronisation; each product is the
+    // sum of its block partials in block order
     tlfea_status dots(const double *V, int nvec, const double *w, double *out)
     {
-        host.resize((size_t)kDotBlocks * kVecChunk);
+        host.resize((size_t)kDotBlocks * nvec);
         for (int k0 = 0; k0 < nvec; k0 += kVecChunk) {
             const int nv = std::min(kVecChunk, nvec - k0);
-            hipError_t e = launch_mdot(V + (int64_t)k0 * N, N, nv, w, N, partial, s);
+            hipError_t e = launch_mdot(V + (int64_t)k0 * N, N, nv, w, N, partial + (int64_t)k0 * kDotBlocks, s);
             if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "dot kernel: %s", hipGetErrorString(e));
-            HIP_TRY(hipMemcpyAsync(host.data(), partial, sizeof(double) * kDotBlocks * nv, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            for (int k = 0; k < nv; ++k) {
-                double t = 0.0;
-                for (int b = 0; b < kDotBlocks; ++b) t += host[(size_t)k * kDotBlocks + b];
-                out[k0 + k] = t;
-            }
+        }
+        HIP_TRY(hipMemcpyAsync(host.data(), partial, sizeof(double) * kDotBlocks * nvec, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int k = 0; k < nvec; ++k) {
+            double t = 0.0;
+            for (int b = 0; b < kDotBlocks; ++b) t += host[(size_t)k * kDotBlocks + b];
+            out[k] = t;
         }
         return TLFEA_OK;
     }

@@ -80,6 +80,12 @@ enum { kModePlain = 0, kModeStep = 1 };
 // the host's launch tables).
 enum { kOpMass = 3 };
 
+// Dot products of the Newton-Krylov step: partial sums per product (one per
+// block of the dot kernel, added in block order on the host) and vectors per
+// launch of the multi-vector kernels.
+constexpr int kDotBlocks = 1024;
+constexpr int kVecChunk = 8;
+
 // The no-allocation forward keeps its shared-node partial sums (three rows
 // of n_part doubles) in a static device array of this many doubles (64 MiB).
 constexpr int64_t kScratchDoubles = int64_t(8) << 20;

@@ -6,17 +6,17 @@
 
 #include <stdint.h>
 
-namespace tlfea {
+#include "tlfea_internal.h"
 
-constexpr int kDotBlocks = 256;   // partial sums per dot product
-constexpr int kVecChunk = 8;      // vectors per launch of the multi-vector kernels
+namespace tlfea {
 
 struct Coeffs {
     double c[kVecChunk];
 };
 
 // partial[k][b] = sum over block b's entries of V_k . w, k < nvec (<= 8),
-// V_k = V + k * ldv.  Block b takes entries b * 256 + t, b * 256 + t +
+// V_k = V + k * ldv.  Block b (of kDotBlocks, four per compute unit, so
+// that enough loads are in flight) takes entries b * 256 + t, b * 256 + t +
 // 256 * kDotBlocks, ...; the block's sum is a fixed tree over its threads.
 template <int NV>
 __global__ __launch_bounds__(256) void k_mdot(const double *__restrict__ V, int64_t ldv, const double *__restrict__ w,
