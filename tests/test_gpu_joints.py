@@ -123,3 +123,22 @@ def test_joint_creation_rejects_bad_input():
     with pytest.raises(TlfeaError) as ei:
         Joints(X, [same])
     assert ei.value.status == -1
+
+
+def test_empty_joint_set():
+    """No joints: the values call writes nothing, the scatter overwrites g
+    with zeros (or leaves it unchanged when accumulating)."""
+    import torch
+
+    from paper_2602_17002_amd.joints import Joints
+    X, _ = synth.box_t10(2, 2, 2, size=(0.2, 0.2, 0.2))
+    J = Joints(X, [])
+    q = to_dev(X)
+    c = J.values(q)
+    assert c.shape[0] == 0
+    g = torch.full_like(q, 3.0)
+    J.scatter(q, None, 1e4, 1e-3, out=g)
+    assert torch.all(g == 0)
+    g = torch.full_like(q, 3.0)
+    J.scatter(q, None, 1e4, 1e-3, out=g, accumulate=True)
+    assert torch.all(g == 3.0)

@@ -205,3 +205,23 @@ def test_q27_full_size_body_whole_outputs_against_oracle():
         e = rel(got, want)
         say("q27", name, "rel", e)
         assert e <= TOL, (name, e)
+
+
+def test_q27_single_element_and_rigid_motion():
+    """One curved Q27 element: every operation against the oracle; under a
+    rigid rotation and translation of the reference the force is zero to
+    rounding."""
+    p = q27_problem("MR", True, n=(1, 1, 1), seed=70, per_elem=True)
+    m = mesh_of(p)
+    x, v, w, dx = to_dev(p.x), to_dev(p.v), to_dev(p.w), to_dev(p.dx)
+    th = p.theta_all()
+    assert rel(to_host(m.internal_force(x, v, to_dev(th))), O.internal_force(*oc(p), p.v)) <= TOL
+    gx, gv, gt = m.vjp(x, v, w, to_dev(th))
+    rx, rv, rt = O.vjp(*oc(p), p.v, p.w)
+    assert rel(to_host(gx), rx) <= TOL and rel(to_host(gv), rv) <= TOL
+    assert rel(to_host(m.jvp(x, v, dx, None, to_dev(th))), O.jvp(*oc(p), p.v, p.dx)) <= TOL
+    R = synth.random_rotation(np.random.default_rng(71))
+    xr = R @ p.X + np.array([[0.3], [-0.2], [0.1]])
+    f = to_host(m.internal_force(to_dev(xr), to_dev(np.zeros_like(p.X)), to_dev(th)))
+    scale = np.abs(to_host(m.internal_force(x, v, to_dev(th)))).max()
+    assert np.abs(f).max() <= 1e-12 * scale

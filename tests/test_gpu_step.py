@@ -207,3 +207,39 @@ def test_newton_steps_converge_quadratically_on_gpu():
         vk, info = m.newton_step(qd, vnd, vk, h, th, fd, restart=60, max_iters=1200, rtol=1e-11)
     say("GPU Newton residuals", norms)
     assert norms[1] <= 0.1 * norms[0] and norms[2] <= 0.01 * norms[1] and norms[3] <= 1e-4 * norms[2]
+
+
+def test_newton_step_argument_errors_and_degenerate_inputs():
+    """A workspace one double short is refused; restart, max_iters and rtol
+    outside their ranges and h <= 0 are refused before any device work; a
+    state that already solves the step (g = 0) returns v unchanged and
+    converged without an iteration."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2602_17002_amd import TlfeaError, _lib
+    p = _with_rho(make_problem(synth.T10, "NH", True, n=(3, 3, 2), seed=96), 1000.0)
+    h = 1e-4
+    q_n, v_n, v, f_ext, _ = _step_inputs(p, 97, h)
+    m = mesh_of(p)
+    args = [to_dev(a) for a in (q_n, v_n, v)]
+    L = _lib.lib()
+    n = C.c_int64()
+    assert L.tlfea_newton_workspace(m.handle, 30, C.byref(n)) == 0
+    short = torch.empty(n.value - 1, dtype=torch.float64, device=args[0].device)
+    with pytest.raises(TlfeaError) as ei:
+        m.newton_step(*args, h, work=short)
+    assert ei.value.status == -2
+    for kw in (dict(restart=0), dict(restart=201), dict(max_iters=0), dict(rtol=-1.0), dict(rtol=float("nan"))):
+        with pytest.raises(TlfeaError) as ei:
+            m.newton_step(*args, h, **kw)
+        assert ei.value.status == -1, kw
+    for bad_h in (0.0, -1e-4, float("inf")):
+        with pytest.raises(TlfeaError):
+            m.newton_step(*args, bad_h)
+    # f_ext = g(v): the residual with it vanishes exactly, nothing to solve
+    g0 = m.step_residual(*args, h)
+    vo, info = m.newton_step(*args, h, f_ext=g0)
+    assert info["converged"] == 1 and info["iters"] == 0 and info["g_norm"] == 0.0
+    assert torch.equal(vo, args[2])
