@@ -1084,20 +1084,23 @@ __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMes
     const int g0 = gid[t.ref];
 #pragma unroll
     for (int k0 = 0; k0 < SPT; k0 += CH) {
-        int g[CH], p[CH];
+        // lanes past the tile's last node load its last node again (a valid
+        // address) and store nothing: unconditional loads issue back to
+        // back, where guarded ones made the compiler wait at every join
+        int g[CH], p[CH], lc[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
             const int l = tid + (k0 + k) * nthr;
-            g[k] = l < t.n_node ? __builtin_nontemporal_load(gid + l) : -1;
-            p[k] = l < t.n_node ? (int)__builtin_nontemporal_load(lpos + l) : 0;
+            lc[k] = l < t.n_node ? l : t.n_node - 1;
+            g[k] = __builtin_nontemporal_load(gid + lc[k]);
+            p[k] = (int)__builtin_nontemporal_load(lpos + lc[k]);
         }
         double v[CH][3 * R::nfield];
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
             const double *xt = m.Xt + cc * m.n_tnode + t.node_begin;
 #pragma unroll
-            for (int k = 0; k < CH; ++k)
-                v[k][R::oX + cc] = g[k] >= 0 ? __builtin_nontemporal_load(xt + tid + (k0 + k) * nthr) : 0.0;
+            for (int k = 0; k < CH; ++k) v[k][R::oX + cc] = __builtin_nontemporal_load(xt + lc[k]);
         }
 #pragma unroll
         for (int f = 1; f < nf; ++f) {
@@ -1106,13 +1109,12 @@ __device__ __forceinline__ void stage_tile(double *__restrict__ sm, const DevMes
             for (int cc = 0; cc < 3; ++cc) {
                 const double o = centre ? field_value<OP, DAMPED, MODE>(f, cc, g0, c, n) : 0.0;
 #pragma unroll
-                for (int k = 0; k < CH; ++k)
-                    v[k][3 * f + cc] = g[k] >= 0 ? field_value<OP, DAMPED, MODE>(f, cc, g[k], c, n) - o : 0.0;
+                for (int k = 0; k < CH; ++k) v[k][3 * f + cc] = field_value<OP, DAMPED, MODE>(f, cc, g[k], c, n) - o;
             }
         }
 #pragma unroll
         for (int k = 0; k < CH; ++k)
-            if (g[k] >= 0) {
+            if (tid + (k0 + k) * nthr < t.n_node) {
                 double *d = sm + (int64_t)p[k] * R::len;
 #pragma unroll
                 for (int j = 0; j < 3 * nf; ++j) d[j] = v[k][j];
@@ -1128,110 +1130,208 @@ __device__ __forceinline__ void load_na(const DevMesh &m, const TileDesc &t, int
     for (int a = 0; a < NEN; ++a) na[a] = (int)__builtin_nontemporal_load(m.conn_local + t.conn_begin + a * te + i) * LEN;
 }
 
-// The tile's assembly tables, copied to LDS while the node records are
-// staged: for every local node its CSR range of element slots and its
-// destination (>= 0: global node written directly; < 0: -1 - partial slot).
+// The tile's assembly tables in LDS, written while the node records are
+// staged.  The element slots a * te + i of the tile form one list, grouped by
+// local node (CSR order, the first entry of every node's group flagged with
+// kSlotHead); thread j sums the entries [j C, j C + C) of that list, C =
+// slot_chunk(NEN, LPE), and cn[j] is the local node of its first entry.
 struct TileCsr {
-    int32_t *ptr;      // [n_node + 1], relative to the tile's first entry
-    int32_t *dst;      // [n_node]
-    uint16_t *slot;    // [nen * n_elem]: element slot a * te + i of each entry
+    uint16_t *cn;      // [nthr]: local node of entry j * C
+    int32_t *dst;      // [n_node]: >= 0 global node written directly; < 0: -1 - partial slot
+    uint16_t *slot;    // [nen * n_elem]: element slot a * te + i of each entry (| kSlotHead)
 };
 
 // LDS layout of a tile: the node records (later overwritten by the element
-// slots of one component), then the assembly tables.
-__device__ __forceinline__ TileCsr csr_layout(double *smem, int nl, int rec_len, int nen, int te, int nc)
+// slots of nc components), then the assembly tables.
+__device__ __forceinline__ TileCsr csr_layout(double *smem, int nl, int rec_len, int nen, int te, int nc, int nthr)
 {
     const int a = max(nl * rec_len, nc * nen * te);   // doubles
     TileCsr c;
-    c.ptr = reinterpret_cast<int32_t *>(smem + a);
-    c.dst = c.ptr + nl + 1;
+    c.cn = reinterpret_cast<uint16_t *>(smem + a);
+    c.dst = reinterpret_cast<int32_t *>(c.cn + nthr);
     c.slot = reinterpret_cast<uint16_t *>(c.dst + nl);
     return c;
 }
 
-// Every load of a thread is issued before its LDS stores (a loop of
-// load-then-store would wait for one global round trip per iteration); the
-// tables are read once per call and loaded non-temporally.  The slot ids
-// are copied as 32-bit words; a tile's entries start at an even global
-// index (the host pads every tile's list to an even length).
+// The tile's assembly tables, in two steps: load() issues the global loads
+// (into registers) and store() writes the LDS tables, so that a kernel can
+// issue the node records' loads in between and both sets are in flight
+// together (store() ends in a loop of data-dependent length, past which the
+// compiler does not move later loads).  The tables are read once per call
+// and loaded non-temporally.  The slot ids are copied as 32-bit words; a
+// tile's entries start at an even global index (the host pads every tile's
+// list to an even length).  The owner of local node l (list range
+// [p0, p1)) writes cn[j] = l for every chunk start j C inside that range.
 template <int NEN, int SPT = kStagePerThread, int LPE = 1>
-__device__ __forceinline__ void stage_csr(const TileCsr &c, const DevMesh &m, const TileDesc &t, int tid, int nthr)
-{
-    const int32_t *gptr = m.lnode_ptr + t.ptr_begin;
-    const int32_t base = gptr[0];
-    int32_t pv[SPT + 1], dv[SPT];
-#pragma unroll
-    for (int k = 0; k <= SPT; ++k) {
-        const int l = tid + k * nthr;
-        pv[k] = l <= t.n_node ? __builtin_nontemporal_load(gptr + l) - base : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-        const int l = tid + k * nthr;
-        dv[k] = l < t.n_node ? __builtin_nontemporal_load(m.lnode_dst + t.node_begin + l) : 0;
-    }
+struct CsrStage {
+    static constexpr int C = slot_chunk(NEN, LPE);
     // NEN * n_elem entries = NEN * n_elem / 2 words over te * LPE threads:
     // at most NEN / (2 LPE) words per thread
-    constexpr int W = (NEN + 2 * LPE - 1) / (2 * LPE);
-    const int n_words = (NEN * t.n_elem + 1) / 2;
-    const uint32_t *gw = reinterpret_cast<const uint32_t *>(m.lnode_slot + base);
+    static constexpr int W = (NEN + 2 * LPE - 1) / (2 * LPE);
+    int32_t p0[SPT], p1[SPT], dv[SPT];
     uint32_t wv[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const int e = tid + k * nthr;
-        wv[k] = e < n_words ? __builtin_nontemporal_load(gw + e) : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k <= SPT; ++k)
-        if (tid + k * nthr <= t.n_node) c.ptr[tid + k * nthr] = pv[k];
-#pragma unroll
-    for (int k = 0; k < SPT; ++k)
-        if (tid + k * nthr < t.n_node) c.dst[tid + k * nthr] = dv[k];
-    uint32_t *sw = reinterpret_cast<uint32_t *>(c.slot);
-#pragma unroll
-    for (int k = 0; k < W; ++k)
-        if (tid + k * nthr < n_words) sw[tid + k * nthr] = wv[k];
-}
 
-// Sum, for every local node, its element slots (CSR order) of the
+    __device__ __forceinline__ void load(const DevMesh &m, const TileDesc &t, int tid, int nthr)
+    {
+        const int32_t *gptr = m.lnode_ptr + t.ptr_begin;
+        const int32_t base = gptr[0];
+        // lanes past the end load the last entry again (stored by nobody):
+        // unconditional loads issue back to back
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int l = tid + k * nthr;
+            const int lc = l < t.n_node ? l : t.n_node - 1;
+            p0[k] = __builtin_nontemporal_load(gptr + lc) - base;
+            p1[k] = __builtin_nontemporal_load(gptr + lc + 1) - base;
+            dv[k] = __builtin_nontemporal_load(m.lnode_dst + t.node_begin + lc);
+        }
+        const int n_words = (NEN * t.n_elem + 1) / 2;
+        const uint32_t *gw = reinterpret_cast<const uint32_t *>(m.lnode_slot + base);
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int e = tid + k * nthr;
+            wv[k] = __builtin_nontemporal_load(gw + (e < n_words ? e : n_words - 1));
+        }
+    }
+
+    __device__ __forceinline__ void store(const TileCsr &c, const TileDesc &t, int tid, int nthr) const
+    {
+        const int n_words = (NEN * t.n_elem + 1) / 2;
+        uint32_t *sw = reinterpret_cast<uint32_t *>(c.slot);
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            if (tid + k * nthr < n_words) sw[tid + k * nthr] = wv[k];
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int l = tid + k * nthr;
+            if (l < t.n_node) {
+                c.dst[l] = dv[k];
+                for (int j = (p0[k] + C - 1) / C; j * C < p1[k]; ++j) c.cn[j] = (uint16_t)l;
+            }
+        }
+    }
+};
+
+// Sum, for every local node, its element slots (list order) of the
 // components r0 .. r0 + NC - 1 (slot region of component r0 + k at
 // k * slot_stride) and write each value to the output (node owned by this
 // tile only) or to the node's partial slot (shared node, partial row
-// 3 * field + r).  The slot list is read eight entries at a time so that the
-// loads of a node are independent.
-template <int NC>
-__device__ __forceinline__ void reduce_components(const DevMesh &m, const TileDesc &t, const TileCsr &c,
-                                                  const double *__restrict__ slot, int slot_stride,
-                                                  double *__restrict__ out, const double *__restrict__ sub,
-                                                  int field, int r0, int tid, int nthr)
+// 3 * field + r).  Thread j walks its C entries once: every node whose group
+// starts and ends inside the chunk is summed and written there; the group
+// running into the chunk from the left (its leading part) is left in LDS
+// for the thread that holds the group's first entry, which adds the leading
+// parts of the following chunks in their order and writes the node.  Every
+// thread walks the same number of entries (a node by node walk took as many
+// rounds as the wave's largest group), and each node's value is the same
+// for every call.  The slot region is free for the leading parts once every
+// thread holds its values (the barrier in between).
+template <int NC, int C, int G>
+__device__ __forceinline__ void reduce_chunks(const DevMesh &m, const TileDesc &t, const TileCsr &c,
+                                              double *__restrict__ slot, int slot_stride,
+                                              double *__restrict__ out, const double *__restrict__ sub,
+                                              int field, int r0, int tid, int nthr, int nen)
 {
-    constexpr int U = 8;
-    for (int l = tid; l < t.n_node; l += nthr) {
-        const int p0 = c.ptr[l], p1 = c.ptr[l + 1];
-        double s[NC];
+    static_assert(NC % G == 0, "component passes");
+    const int E = nen * t.n_elem;
+    const int e0 = tid * C;
+    const int ne = min(C, E - e0);   // <= 0: no entries
+    const bool cont = e0 + C < E;    // a next chunk exists
+    int l = 0, next = -1;
+    uint32_t raw[C];
+    if (ne > 0) {
+        l = c.cn[tid];
+        if (cont) next = c.cn[tid + 1];
+    }
 #pragma unroll
-        for (int k = 0; k < NC; ++k) s[k] = 0.0;
-        for (int p = p0; p < p1; p += U) {
-            int id[U];
+    for (int u = 0; u < C; ++u) raw[u] = u < ne ? c.slot[e0 + u] : 0u;
+    // node of every entry, and the destination of the group each head closes
+    // (the leading group has none here)
+    const bool lead = ne > 0 && !(raw[0] & kSlotHead);   // the chunk starts inside a group
+    int nid[C], dc[C];
+    {
+        int cur = l;
 #pragma unroll
-            for (int u = 0; u < U; ++u) id[u] = p + u < p1 ? (int)c.slot[p + u] : -1;
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (id[u] >= 0) {
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) s[k] += slot[k * slot_stride + id[u]];
-                }
+        for (int u = 0; u < C; ++u) {
+            if (u > 0 && (raw[u] & kSlotHead)) ++cur;
+            nid[u] = cur;
         }
-        const int d = c.dst[l];
+    }
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            if (d >= 0) {
-                const int64_t o = (r0 + k) * m.n_nodes + d;
-                out[o] = sub ? s[k] - sub[o] : s[k];
-            } else {
-                m.part[(int64_t)(3 * field + r0 + k) * m.n_part + (-1 - d)] = s[k];
+    for (int u = 0; u < C; ++u) {
+        const bool closes = u > 0 && u < ne && (raw[u] & kSlotHead) && !(lead && nid[u] - 1 == l);
+        dc[u] = closes ? c.dst[nid[u] - 1] : 0;
+    }
+    const int last = ne > 0 ? nid[C - 1] : 0;             // the chunk's last group
+    const bool mine = ne > 0 && !(lead && last == l);      // ... starts in this chunk
+    const bool owner = mine && next == last;               // ... and runs on
+    const int dlast = mine ? c.dst[last] : 0;
+    auto put = [&](int d, int r, double v) {
+        if (d >= 0) {
+            const int64_t o = (r0 + r) * m.n_nodes + d;
+            out[o] = sub ? v - sub[o] : v;
+        } else {
+            m.part[(int64_t)(3 * field + r0 + r) * m.n_part + (-1 - d)] = v;
+        }
+    };
+    // G components per pass over the chunk (fewer values in flight where
+    // other accumulators are still live)
+    double lv[NC], own[NC];
+#pragma unroll
+    for (int r1 = 0; r1 < NC; r1 += G) {
+        double v[C][G];
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+            const int id = (int)(raw[u] & (kSlotHead - 1));
+#pragma unroll
+            for (int g = 0; g < G; ++g) v[u][g] = u < ne ? slot[(r1 + g) * slot_stride + id] : 0.0;
+        }
+        double run[G], lp[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) run[g] = lp[g] = 0.0;
+        bool inlead = lead;
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+            if (u < ne) {
+                if (u > 0 && (raw[u] & kSlotHead)) {
+                    if (inlead) {
+#pragma unroll
+                        for (int g = 0; g < G; ++g) lp[g] = run[g];
+                        inlead = false;
+                    } else {
+#pragma unroll
+                        for (int g = 0; g < G; ++g) put(dc[u], r1 + g, run[g]);
+                    }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) run[g] = 0.0;
+                }
+#pragma unroll
+                for (int g = 0; g < G; ++g) run[g] += v[u][g];
             }
         }
+        // the last group: the whole chunk (a leading part), a finished
+        // group, or a group that runs into the next chunks
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (inlead) lp[g] = run[g];
+            else if (mine && !owner) put(dlast, r1 + g, run[g]);
+            lv[r1 + g] = lp[g];
+            own[r1 + g] = run[g];
+        }
+    }
+    __syncthreads();
+    if (lead) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) slot[r * nthr + tid] = lv[r];
+    }
+    __syncthreads();
+    if (owner) {
+        // chunk tid + k starts inside the group while cn[tid + k] == last
+        for (int k = 1; tid + k < nthr && (tid + k) * C < E && c.cn[tid + k] == last; ++k) {
+#pragma unroll
+            for (int r = 0; r < NC; ++r) own[r] += slot[r * nthr + tid + k];
+        }
+#pragma unroll
+        for (int r = 0; r < NC; ++r) put(dlast, r, own[r]);
     }
 }
 
@@ -1239,7 +1339,7 @@ __device__ __forceinline__ void reduce_components(const DevMesh &m, const TileDe
 // round (the host picks NC so that NC x NEN x te slot doubles fit the
 // workgroup's LDS); the slots a * te + i overwrite the node records, which
 // are dead once every lane is done.
-template <int NEN, int NC, int LPE>
+template <int NEN, int NC, int LPE, bool LEAN>
 __device__ __forceinline__ void assemble_nc(const DevMesh &m, const TileDesc &t, const TileCsr &c,
                                             double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
                                             double *__restrict__ out, const double *__restrict__ sub, int field,
@@ -1259,23 +1359,25 @@ __device__ __forceinline__ void assemble_nc(const DevMesh &m, const TileDesc &t,
                 }
         }
         __syncthreads();
-        if (r0 + NC <= 3) reduce_components<NC>(m, t, c, sm, stride, out, sub, field, r0, tid, nthr);
-        else reduce_components<(3 % NC) ? (3 % NC) : 1>(m, t, c, sm, stride, out, sub, field, r0, tid, nthr);
+        constexpr int C = slot_chunk(NEN, LPE);
+        if (r0 + NC <= 3) reduce_chunks<NC, C, LEAN ? 1 : NC>(m, t, c, sm, stride, out, sub, field, r0, tid, nthr, NEN);
+        else reduce_chunks<(3 % NC) ? (3 % NC) : 1, C, 1>(m, t, c, sm, stride, out, sub, field, r0, tid, nthr, NEN);
     }
 }
 
 // LPE lanes per element (Q27: 2): every lane holds its element's whole
 // vector (the lanes' sums, see lane_sum) and the first lane of each element
-// writes its slots.
-template <int NEN, int LPE = 1>
+// writes its slots.  LEAN: one component per pass of the reduction (for
+// kernels that keep other accumulators live meanwhile).
+template <int NEN, int LPE = 1, bool LEAN = false>
 __device__ __forceinline__ void assemble(const DevMesh &m, const TileDesc &t, const TileCsr &c,
                                          double *__restrict__ sm, const double (&fe)[NEN][3], bool active,
                                          double *__restrict__ out, int field, int tid, int te, int nc,
                                          const double *__restrict__ sub = nullptr)
 {
-    if (nc >= 3) assemble_nc<NEN, 3, LPE>(m, t, c, sm, fe, active, out, sub, field, tid, te);
-    else if (nc == 2) assemble_nc<NEN, 2, LPE>(m, t, c, sm, fe, active, out, sub, field, tid, te);
-    else assemble_nc<NEN, 1, LPE>(m, t, c, sm, fe, active, out, sub, field, tid, te);
+    if (nc >= 3) assemble_nc<NEN, 3, LPE, LEAN>(m, t, c, sm, fe, active, out, sub, field, tid, te);
+    else if (nc == 2) assemble_nc<NEN, 2, LPE, LEAN>(m, t, c, sm, fe, active, out, sub, field, tid, te);
+    else assemble_nc<NEN, 1, LPE, LEAN>(m, t, c, sm, fe, active, out, sub, field, tid, te);
 }
 
 // Sum of the partial element vectors of an element's LPE lanes (neighbours
@@ -1334,9 +1436,11 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     // staging issues long-latency loads: its waves go first while other
     // tiles on the compute unit compute
     __builtin_amdgcn_s_setprio(3);
-    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
-    stage_csr<NEN, stage_per_thread(ELEM), LPE>(csr, m, t, tid, nthr);
+    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc, nthr);
+    CsrStage<NEN, stage_per_thread(ELEM), LPE> cs;
+    cs.load(m, t, tid, nthr);
     stage_tile<kOpFwd, DAMPED, MODE, true, stage_per_thread(ELEM)>(smem, m, c, t, tid, nthr);
+    cs.store(csr, t, tid, nthr);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double fe[NEN][3];
@@ -1374,9 +1478,11 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     // staging issues long-latency loads: its waves go first while other
     // tiles on the compute unit compute
     __builtin_amdgcn_s_setprio(3);
-    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
-    stage_csr<NEN, stage_per_thread(ELEM), LPE>(csr, m, t, tid, nthr);
+    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc, nthr);
+    CsrStage<NEN, stage_per_thread(ELEM), LPE> cs;
+    cs.load(m, t, tid, nthr);
     stage_tile<kOpVjp, DAMPED, kModePlain, WANT_GT && ELEM == kT10, stage_per_thread(ELEM)>(smem, m, c, t, tid, nthr);
+    cs.store(csr, t, tid, nthr);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double gx[NEN][3], gv[NEN][3], gt[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1409,7 +1515,8 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
         c.gtheta[3 * m.n_elem + uid] = DAMPED ? gt[3] : 0.0;
         c.gtheta[4 * m.n_elem + uid] = DAMPED ? gt[4] : 0.0;
     }
-    if (c.out0) assemble<NEN, LPE>(m, t, csr, smem, gx, active, c.out0, 0, tid, te, nc);
+    // gv (and the parameter gradients) are still live while gx is reduced
+    if (c.out0) assemble<NEN, LPE, DAMPED>(m, t, csr, smem, gx, active, c.out0, 0, tid, te, nc);
     if (c.out1) {
         if constexpr (DAMPED) assemble<NEN, LPE>(m, t, csr, smem, gv, active, c.out1, 1, tid, te, nc);
         else zero_nodes(m, t, csr, c.out1, 1, tid, nthr);
@@ -1438,9 +1545,11 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) __attribute__((amdgpu_waves_per_eu(wa
     // staging issues long-latency loads: its waves go first while other
     // tiles on the compute unit compute
     __builtin_amdgcn_s_setprio(3);
-    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc);
-    stage_csr<NEN, stage_per_thread(ELEM), LPE>(csr, m, t, tid, nthr);
+    const TileCsr csr = csr_layout(smem, nl, R::len, NEN, te, nc, nthr);
+    CsrStage<NEN, stage_per_thread(ELEM), LPE> cs;
+    cs.load(m, t, tid, nthr);
     stage_tile<kOpJvp, DAMPED, MODE, false, stage_per_thread(ELEM)>(smem, m, c, t, tid, nthr);
+    cs.store(csr, t, tid, nthr);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     double df[NEN][3];
@@ -1476,9 +1585,10 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_mass(DevMesh m, CallArgs c, in
     if (ti < 0) return;
     const TileDesc t = m.tiles[tile0 + ti];
     const int tid = threadIdx.x, ie = tid / LPE, part = tid % LPE, nthr = te * LPE;
-    const TileCsr csr = csr_layout(smem, nl, LEN, NEN, te, nc);
+    const TileCsr csr = csr_layout(smem, nl, LEN, NEN, te, nc, nthr);
     constexpr int SPT = stage_per_thread(ELEM);
-    stage_csr<NEN, SPT, LPE>(csr, m, t, tid, nthr);
+    CsrStage<NEN, SPT, LPE> cs;
+    cs.load(m, t, tid, nthr);
     {
         const int32_t *gid = m.lnode_gid + t.node_begin;
         const uint16_t *lpos = m.lnode_pos + t.node_begin;
@@ -1487,19 +1597,21 @@ __global__ __launch_bounds__(TLFEA_MAX_TE) void k_mass(DevMesh m, CallArgs c, in
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
             const int l = tid + k * nthr;
-            g[k] = l < t.n_node ? __builtin_nontemporal_load(gid + l) : -1;
-            p[k] = l < t.n_node ? (int)__builtin_nontemporal_load(lpos + l) : 0;
+            const int lc = l < t.n_node ? l : t.n_node - 1;
+            g[k] = __builtin_nontemporal_load(gid + lc);
+            p[k] = (int)__builtin_nontemporal_load(lpos + lc);
         }
 #pragma unroll
         for (int k = 0; k < SPT; ++k)
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) v[k][cc] = g[k] >= 0 ? c.x[cc * m.n_nodes + g[k]] : 0.0;
+            for (int cc = 0; cc < 3; ++cc) v[k][cc] = c.x[cc * m.n_nodes + g[k]];
 #pragma unroll
         for (int k = 0; k < SPT; ++k)
-            if (g[k] >= 0)
+            if (tid + k * nthr < t.n_node)
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) smem[p[k] * LEN + cc] = v[k][cc];
     }
+    cs.store(csr, t, tid, nthr);
     __syncthreads();
     double fe[NEN][3];
 #pragma unroll

@@ -421,20 +421,23 @@ static int nl_limit(int elem, int law, int te, int damped, int64_t lds_dev)
     // only the LDS limit.
     if (te == 256 && elem != kQ27) nl = std::min<int64_t>(nl, 600);
     for (int kind : kKinds) {
-        const int64_t fixed = 4 + (int64_t)nen * te * 2;
-        const int64_t per_node = 8 * (int64_t)kind_record_len(kind, damped != 0) + 8;
+        const int64_t fixed = (int64_t)lanes_per_elem(elem) * te * 2 + (int64_t)nen * te * 2;
+        const int64_t per_node = 8 * (int64_t)kind_record_len(kind, damped != 0) + 4;
         nl = std::min(nl, (lds_budget(kind, elem, law, damped, te, lds_dev) - fixed) / per_node);
     }
     return (int)nl;
 }
 
 // LDS of one workgroup: the node records (reused for the element slots of
-// nc components), then the tile's assembly tables (see the kernels).
+// nc components), then the tile's assembly tables (see the kernels): the
+// first node of every thread's chunk of the slot list, every node's
+// destination, and the slot list.
 static size_t lds_bytes(const ClassRange &c, int kind, int nc)
 {
     const size_t records = (size_t)c.nl_cap * kind_record_len(kind, c.damped != 0);
     const size_t slots = (size_t)nc * nen_of(c.elem) * c.te;
-    const size_t tables = (size_t)(2 * c.nl_cap + 1) * sizeof(int32_t) + (size_t)nen_of(c.elem) * c.te * sizeof(uint16_t);
+    const size_t tables = (size_t)lanes_per_elem(c.elem) * c.te * sizeof(uint16_t) + (size_t)c.nl_cap * sizeof(int32_t) +
+                          (size_t)nen_of(c.elem) * c.te * sizeof(uint16_t);
     return std::max(records, slots) * sizeof(double) + tables;
 }
 
@@ -793,7 +796,9 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                 }
                 // per-node slot lists (CSR); visiting slots a * te + i in
                 // increasing order leaves every list sorted.  Each tile's list
-                // starts at an even index (the kernels copy it as 32-bit words).
+                // starts at an even index (the kernels copy it as 32-bit words),
+                // and the first entry of every node's group is flagged (the
+                // kernels split the tile's list into equal chunks).
                 {
                     if (hb.lnode_slot.size() & 1) hb.lnode_slot.push_back(0);
                     const size_t nn = nodes.size(), base = hb.lnode_slot.size();
@@ -809,6 +814,7 @@ static tlfea_status build_tiles(int64_t n_nodes, const double *X, int n_blocks, 
                             const int l = hb.conn_local[t.conn_begin + (size_t)a * te + i];
                             hb.lnode_slot[base + cnt[l]++] = (uint16_t)(a * te + i);
                         }
+                    for (size_t l = 0; l < nn; ++l) hb.lnode_slot[hb.lnode_ptr[t.ptr_begin + l]] |= kSlotHead;
                 }
                 // LDS record positions; the elements address records by position
                 {

@@ -34,6 +34,13 @@ constexpr int kStagePerThread = 3;
 constexpr int kStageRound = 6;
 constexpr int stage_per_thread(int elem) { return elem == 2 ? 6 : kStagePerThread; }
 
+// Slot lists: the first entry of every node's group carries this flag; the
+// slot ids themselves (a * te + i) stay below it.
+constexpr uint16_t kSlotHead = 0x8000;
+// Entries of a tile's slot list summed by one thread: the elements' entries
+// spread evenly over the tile's te * LPE threads.
+constexpr int slot_chunk(int nen, int lpe) { return (nen + lpe - 1) / lpe; }
+
 struct BlockDesc {
     double theta[5];
     int32_t elem, law, damped, pad;
@@ -47,7 +54,7 @@ struct DevMesh {
     const uint16_t *lnode_pos;    // LDS record position of each local node (a permutation)
     const int32_t *lnode_dst;     // >= 0: global node written directly; < 0: -1 - partial slot
     const int32_t *lnode_ptr;     // CSR offsets into lnode_slot
-    const uint16_t *lnode_slot;   // element-force slot = a * te + i
+    const uint16_t *lnode_slot;   // element-force slot = a * te + i (| kSlotHead on a group's first entry)
     const int32_t *elem_uid;      // caller's element id of each internal element
     const BlockDesc *blocks;
     const double *Xt;             // [3][n_tnode] reference coordinates of every tile node,

@@ -163,8 +163,74 @@ int main(int argc, char **argv)
             const int p0 = hb.lnode_ptr[t.ptr_begin + l], p1 = hb.lnode_ptr[t.ptr_begin + l + 1];
             CHECK(p1 - p0 == (int)refs[l].size(), "tile %zu node %d has %d slots, expected %zu", ti, l, p1 - p0, refs[l].size());
             std::sort(refs[l].begin(), refs[l].end());
-            for (int k = p0; k < p1; ++k)
-                CHECK(hb.lnode_slot[k] == refs[l][k - p0], "tile %zu node %d slot list differs", ti, l);
+            for (int k = p0; k < p1; ++k) {
+                CHECK((hb.lnode_slot[k] & (kSlotHead - 1)) == refs[l][k - p0], "tile %zu node %d slot list differs", ti, l);
+                CHECK(((hb.lnode_slot[k] & kSlotHead) != 0) == (k == p0), "tile %zu node %d group flag at entry %d", ti, l, k - p0);
+            }
+        }
+        // the kernels' chunked reduction of the slot list, replayed: thread j
+        // sums entries [j C, j C + C); groups that start in a chunk are
+        // finished there or by that chunk's thread from the following
+        // chunks' leading parts.  Entry values are the slot ids + 1 (exact
+        // sums); every node must come out once with its own sum.
+        {
+            const int lpe = lanes_per_elem(blocks[b].elem), C = slot_chunk(nen, lpe), nthr = T * lpe;
+            const int E = nen * t.n_elem;
+            const int base = hb.lnode_ptr[t.ptr_begin];
+            CHECK(E <= C * nthr, "tile %zu: %d slot entries over %d threads of %d", ti, E, nthr, C);
+            CHECK(hb.lnode_ptr[t.ptr_begin + t.n_node] - base == E, "tile %zu: list length", ti);
+            std::vector<int> cn(nthr, -1);
+            for (int l = 0; l < t.n_node; ++l) {
+                const int q0 = hb.lnode_ptr[t.ptr_begin + l] - base, q1 = hb.lnode_ptr[t.ptr_begin + l + 1] - base;
+                for (int j = (q0 + C - 1) / C; j * C < q1; ++j) {
+                    CHECK(j < nthr && cn[j] < 0, "tile %zu chunk %d start claimed twice", ti, j);
+                    cn[j] = l;
+                }
+            }
+            auto val = [&](int e) { return (double)(hb.lnode_slot[base + e] & (kSlotHead - 1)) + 1.0; };
+            auto head = [&](int e) { return (hb.lnode_slot[base + e] & kSlotHead) != 0; };
+            std::vector<double> got(t.n_node, 0.0), want(t.n_node, 0.0), leadv(nthr, 0.0);
+            std::vector<int> writes(t.n_node, 0);
+            for (int e = 0; e < E; ++e) {
+                int l = 0;
+                while (l + 1 < t.n_node && hb.lnode_ptr[t.ptr_begin + l + 1] - base <= e) ++l;
+                want[l] += val(e);
+            }
+            std::vector<int> owner_of(nthr, -1);
+            std::vector<double> own(nthr, 0.0);
+            for (int j = 0; j < nthr; ++j) {
+                const int e0 = j * C, ne = std::min(C, E - e0);
+                if (ne <= 0) continue;
+                CHECK(cn[j] >= 0, "tile %zu chunk %d has no node", ti, j);
+                const int l = cn[j];
+                const int next = e0 + C < E ? cn[j + 1] : -1;
+                const bool lead = !head(e0);
+                int cur = l;
+                double run = 0.0;
+                bool inlead = lead;
+                for (int u = 0; u < ne; ++u) {
+                    if (u > 0 && head(e0 + u)) {
+                        if (inlead) { leadv[j] = run; inlead = false; }
+                        else { CHECK(cur < t.n_node, "tile %zu node index", ti); got[cur] += run; writes[cur]++; }
+                        ++cur;
+                        run = 0.0;
+                    }
+                    run += val(e0 + u);
+                }
+                if (inlead) leadv[j] = run;
+                else if (next == cur) { owner_of[j] = cur; own[j] = run; }
+                else { got[cur] += run; writes[cur]++; }
+            }
+            for (int j = 0; j < nthr; ++j) {
+                if (owner_of[j] < 0) continue;
+                double v = own[j];
+                for (int k = 1; j + k < nthr && (j + k) * C < E && cn[j + k] == owner_of[j]; ++k) v += leadv[j + k];
+                got[owner_of[j]] += v;
+                writes[owner_of[j]]++;
+            }
+            for (int l = 0; l < t.n_node; ++l)
+                CHECK(writes[l] == 1 && got[l] == want[l], "tile %zu node %d: written %d times, sum %g (expected %g)", ti, l,
+                      writes[l], got[l], want[l]);
         }
         // gather model: the placed positions against the sorted order
         const int nq = nq_of(blocks[b].elem);
