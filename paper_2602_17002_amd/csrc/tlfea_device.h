@@ -1216,15 +1216,17 @@ struct CsrStage {
 // components r0 .. r0 + NC - 1 (slot region of component r0 + k at
 // k * slot_stride) and write each value to the output (node owned by this
 // tile only) or to the node's partial slot (shared node, partial row
-// 3 * field + r).  Thread j walks its C entries once: every node whose group
-// starts and ends inside the chunk is summed and written there; the group
-// running into the chunk from the left (its leading part) is left in LDS
-// for the thread that holds the group's first entry, which adds the leading
-// parts of the following chunks in their order and writes the node.  Every
-// thread walks the same number of entries (a node by node walk took as many
-// rounds as the wave's largest group), and each node's value is the same
-// for every call.  The slot region is free for the leading parts once every
-// thread holds its values (the barrier in between).
+// 3 * field + r).  Thread j walks its C entries once (a node by node walk
+// took as many rounds as the wave's largest group): every group that starts
+// and ends inside the chunk is summed there; the part of a group running
+// into the chunk from the left (its leading part) is finished by the thread
+// that holds the group's first entry, which adds the leading parts of the
+// following chunks in their order.  Each node's value is therefore the same
+// in every call.  A component's slot region is free once every thread holds
+// its values (a barrier): the node sums go there at the node's index, the
+// leading parts after them, and a node-parallel pass writes the results
+// out.  G components per pass (fewer values in flight where other
+// accumulators are still live).
 template <int NC, int C, int G>
 __device__ __forceinline__ void reduce_chunks(const DevMesh &m, const TileDesc &t, const TileCsr &c,
                                               double *__restrict__ slot, int slot_stride,
@@ -1232,22 +1234,28 @@ __device__ __forceinline__ void reduce_chunks(const DevMesh &m, const TileDesc &
                                               int field, int r0, int tid, int nthr, int nen)
 {
     static_assert(NC % G == 0, "component passes");
-    const int E = nen * t.n_elem;
+    static_assert(C % 2 == 0, "chunks start at even entries (the list is read as 32-bit words)");
+    const int E = nen * t.n_elem, nl = t.n_node;
     const int e0 = tid * C;
     const int ne = min(C, E - e0);   // <= 0: no entries
-    const bool cont = e0 + C < E;    // a next chunk exists
-    int l = 0, next = -1;
+    // unconditional LDS reads (clamped to the tables), masked afterwards
+    const int ct = min(tid, (E - 1) / C);
+    const int l = c.cn[ct];
+    const int nx = c.cn[min(ct + 1, (E - 1) / C)];
+    const int next = ne > 0 && e0 + C < E ? nx : -1;
     uint32_t raw[C];
-    if (ne > 0) {
-        l = c.cn[tid];
-        if (cont) next = c.cn[tid + 1];
-    }
+    {
+        const uint32_t *sw = reinterpret_cast<const uint32_t *>(c.slot);
+        const int w0 = e0 >> 1, wl = (E - 1) >> 1;
 #pragma unroll
-    for (int u = 0; u < C; ++u) raw[u] = u < ne ? c.slot[e0 + u] : 0u;
-    // node of every entry, and the destination of the group each head closes
-    // (the leading group has none here)
+        for (int k = 0; k < C / 2; ++k) {
+            const uint32_t wd = sw[min(w0 + k, wl)];
+            raw[2 * k] = 2 * k < ne ? (wd & 0xffffu) : 0u;
+            raw[2 * k + 1] = 2 * k + 1 < ne ? (wd >> 16) : 0u;
+        }
+    }
     const bool lead = ne > 0 && !(raw[0] & kSlotHead);   // the chunk starts inside a group
-    int nid[C], dc[C];
+    int nid[C];   // node of every entry
     {
         int cur = l;
 #pragma unroll
@@ -1256,26 +1264,9 @@ __device__ __forceinline__ void reduce_chunks(const DevMesh &m, const TileDesc &
             nid[u] = cur;
         }
     }
-#pragma unroll
-    for (int u = 0; u < C; ++u) {
-        const bool closes = u > 0 && u < ne && (raw[u] & kSlotHead) && !(lead && nid[u] - 1 == l);
-        dc[u] = closes ? c.dst[nid[u] - 1] : 0;
-    }
-    const int last = ne > 0 ? nid[C - 1] : 0;             // the chunk's last group
-    const bool mine = ne > 0 && !(lead && last == l);      // ... starts in this chunk
-    const bool owner = mine && next == last;               // ... and runs on
-    const int dlast = mine ? c.dst[last] : 0;
-    auto put = [&](int d, int r, double v) {
-        if (d >= 0) {
-            const int64_t o = (r0 + r) * m.n_nodes + d;
-            out[o] = sub ? v - sub[o] : v;
-        } else {
-            m.part[(int64_t)(3 * field + r0 + r) * m.n_part + (-1 - d)] = v;
-        }
-    };
-    // G components per pass over the chunk (fewer values in flight where
-    // other accumulators are still live)
-    double lv[NC], own[NC];
+    const int last = nid[C - 1];                              // the chunk's last group
+    const bool owner = ne > 0 && !(lead && last == l) && next == last;   // starts here, runs on
+    double own[NC];
 #pragma unroll
     for (int r1 = 0; r1 < NC; r1 += G) {
         double v[C][G];
@@ -1283,55 +1274,55 @@ __device__ __forceinline__ void reduce_chunks(const DevMesh &m, const TileDesc &
         for (int u = 0; u < C; ++u) {
             const int id = (int)(raw[u] & (kSlotHead - 1));
 #pragma unroll
-            for (int g = 0; g < G; ++g) v[u][g] = u < ne ? slot[(r1 + g) * slot_stride + id] : 0.0;
-        }
-        double run[G], lp[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) run[g] = lp[g] = 0.0;
-        bool inlead = lead;
-#pragma unroll
-        for (int u = 0; u < C; ++u) {
-            if (u < ne) {
-                if (u > 0 && (raw[u] & kSlotHead)) {
-                    if (inlead) {
-#pragma unroll
-                        for (int g = 0; g < G; ++g) lp[g] = run[g];
-                        inlead = false;
-                    } else {
-#pragma unroll
-                        for (int g = 0; g < G; ++g) put(dc[u], r1 + g, run[g]);
-                    }
-#pragma unroll
-                    for (int g = 0; g < G; ++g) run[g] = 0.0;
-                }
-#pragma unroll
-                for (int g = 0; g < G; ++g) run[g] += v[u][g];
+            for (int g = 0; g < G; ++g) {
+                const double x = slot[(r1 + g) * slot_stride + id];
+                v[u][g] = u < ne ? x : 0.0;
             }
         }
-        // the last group: the whole chunk (a leading part), a finished
-        // group, or a group that runs into the next chunks
+        __syncthreads();   // these components' slots are read: their regions take the sums
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (inlead) lp[g] = run[g];
-            else if (mine && !owner) put(dlast, r1 + g, run[g]);
-            lv[r1 + g] = lp[g];
-            own[r1 + g] = run[g];
-        }
-    }
-    __syncthreads();
-    if (lead) {
+            double *sums = slot + (r1 + g) * slot_stride;   // [nl] node sums, then [nthr] leading parts
+            // entries past the chunk's end have no flag and the value 0
+            double run = 0.0;
+            bool inlead = lead;
 #pragma unroll
-        for (int r = 0; r < NC; ++r) slot[r * nthr + tid] = lv[r];
+            for (int u = 0; u < C; ++u) {
+                const bool h = u > 0 && (raw[u] & kSlotHead);
+                if (h) sums[inlead ? nl + tid : nid[u] - 1] = run;
+                run = (h ? 0.0 : run) + v[u][g];
+                inlead = inlead && !h;
+            }
+            // the last group: a leading part (the whole chunk), a finished
+            // group, or one that runs into the next chunks
+            if (ne > 0 && !owner) sums[inlead ? nl + tid : last] = run;
+            own[r1 + g] = run;
+        }
     }
     __syncthreads();
     if (owner) {
         // chunk tid + k starts inside the group while cn[tid + k] == last
-        for (int k = 1; tid + k < nthr && (tid + k) * C < E && c.cn[tid + k] == last; ++k) {
 #pragma unroll
-            for (int r = 0; r < NC; ++r) own[r] += slot[r * nthr + tid + k];
+        for (int r = 0; r < NC; ++r) {
+            const double *sums = slot + r * slot_stride;
+            double s = own[r];
+            for (int k = 1; tid + k < nthr && (tid + k) * C < E && c.cn[tid + k] == last; ++k) s += sums[nl + tid + k];
+            slot[r * slot_stride + last] = s;
         }
+    }
+    __syncthreads();
+    for (int q = tid; q < nl; q += nthr) {
+        const int d = c.dst[q];
 #pragma unroll
-        for (int r = 0; r < NC; ++r) put(dlast, r, own[r]);
+        for (int r = 0; r < NC; ++r) {
+            const double v = slot[r * slot_stride + q];
+            if (d >= 0) {
+                const int64_t o = (r0 + r) * m.n_nodes + d;
+                out[o] = sub ? v - sub[o] : v;
+            } else {
+                m.part[(int64_t)(3 * field + r0 + r) * m.n_part + (-1 - d)] = v;
+            }
+        }
     }
 }
 
