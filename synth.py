@@ -102,6 +102,27 @@ def box_t10(nx, ny, nz, size=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
     return X, conn.reshape(ncell * 6, 10).astype(np.int32)
 
 
+def fan_t10(n_elem, cell, rng):
+    """``n_elem`` straight-sided T10 that share one corner, node 0, and no
+    other node: node 0 is in every element (one very long slot list per tile,
+    and a node shared by many tiles).  Element e is the corner tetrahedron
+    (0, cell e_x, cell e_y, cell e_z) scaled by U[0.7, 1.3] and turned by a
+    random rotation (positive orientation kept); the elements overlap in
+    space, which the per-element kinematics do not see.
+    Returns (X [3][1 + 9 n_elem] float64, conn [n_elem][10] int32)."""
+    X = np.zeros((3, 1 + 9 * n_elem))
+    conn = np.empty((n_elem, 10), dtype=np.int32)
+    for e in range(n_elem):
+        R = random_rotation(rng)
+        corners = [np.zeros(3)] + [R @ (cell * rng.uniform(0.7, 1.3) * np.eye(3)[k]) for k in range(3)]
+        ids = [0] + [1 + 9 * e + k for k in range(9)]
+        pts = corners + [0.5 * (corners[a] + corners[b]) for (a, b) in _T10_EDGES]
+        for n in range(1, 10):
+            X[:, ids[n]] = pts[n]
+        conn[e] = ids
+    return X, conn
+
+
 def box_h8(nx, ny, nz, size=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
     """Structured box of nx*ny*nz H8 cells (node order: lexicographic, i fastest)."""
     NX, NY, NZ = nx + 1, ny + 1, nz + 1

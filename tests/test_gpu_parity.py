@@ -284,6 +284,33 @@ def test_degenerate_meshes():
     assert np.all(to_host(m.internal_force(to_dev(x), to_dev(v))) == 0)
 
 
+@pytest.mark.parametrize("tile", [64, 256])
+def test_node_in_every_element(tile):
+    """A fan of 700 T10 around one shared corner node: that node's slot group
+    spans several threads' chunks in every tile (the reduction's long case)
+    and it is shared by every tile.  Forward, adjoint and tangent against
+    the oracle."""
+    rng = np.random.default_rng(61)
+    X, conn = synth.fan_t10(700, 0.02, rng)
+    x = X + rng.normal(0, 2e-3, X.shape)
+    v = rng.normal(0, 0.5, X.shape)
+    b = synth.Block(synth.T10, synth.NH, conn, LAWS["NH"][1], damped=True)
+    p = synth.Problem("fan", X, x, v, [b], cell=0.02)
+    p.w = rng.standard_normal(X.shape)
+    dx = rng.standard_normal(X.shape) * 0.02
+    dv = rng.standard_normal(X.shape)
+    say("fan", "tile", tile, "elements", p.n_elem)
+    m = mesh_of(p, tile=tile)
+    assert m.info()["n_tiles"] >= 700 // 66
+    f = to_host(m.internal_force(to_dev(x), to_dev(v)))
+    assert rel(f, O.internal_force(*oc(p), v)) <= TOL
+    gx, gv, _ = m.vjp(to_dev(x), to_dev(v), to_dev(p.w), want_theta=False)
+    rx, rv, _ = O.vjp(*oc(p), v, p.w)
+    assert rel(to_host(gx), rx) <= TOL and rel(to_host(gv), rv) <= TOL
+    df = to_host(m.jvp(to_dev(x), to_dev(v), to_dev(dx), to_dev(dv)))
+    assert rel(df, O.jvp(*oc(p), v, dx, dv)) <= TOL
+
+
 def test_node_order_renumbering():
     """tlfea_node_order is a permutation; a mesh built from the renumbered
     problem gives the renumbered outputs (to rounding) and matches the oracle."""

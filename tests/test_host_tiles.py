@@ -78,6 +78,19 @@ def test_q27_body_tiles(harness, tmp_path, tile):
     assert s["tiles"] >= conn.shape[0] // tile
 
 
+@pytest.mark.parametrize("tile", [64, 256])
+def test_node_in_every_element(harness, tmp_path, tile):
+    """One node in all 700 elements (a fan of T10 around it): in every tile
+    its slot group is the tile's whole first column of entries and spans
+    several threads' chunks (the chunked reduction's long case), and it is
+    shared by every tile (one partial per tile)."""
+    X, conn = synth.fan_t10(700, 0.02, np.random.default_rng(3))
+    b = synth.Block(synth.T10, synth.NH, conn, np.array([1.7e6, 0, 1.7e7, 1e4, 0]), damped=True)
+    b.tile_elems = tile
+    s = run(harness, tmp_path, X, [b])
+    assert s["tiles"] >= 700 // 66 and s["shared"] == 1 and s["partials"] == s["tiles"]
+
+
 def test_multibody_mixed_blocks_and_keep_order(harness, tmp_path):
     p = synth.config_multibody(6, 150, 2500, seed=21)
     for flags in (0, 4):   # default order, TLFEA_KEEP_ORDER
