@@ -15,18 +15,38 @@
 
 namespace tlfea {
 
-// r of point p of joint j: sum over the hosting element's nodes
+// r of point p of joint j: sum over the hosting element's nodes, in slot
+// order.  The slots are read kSlotBatch at a time with every load of a batch
+// in flight together (slot by slot, each slot waited for its shape value and
+// node id, then for the node's coordinates: two dependent round trips per
+// slot); slots past nmax reread the last one and unused slots (shape value 0,
+// node 0) are not added.
+constexpr int kSlotBatch = 10;
+
 __device__ __forceinline__ void point_eval(const DevJoints &J, const double *__restrict__ q, int p, int64_t j,
                                            double r[3])
 {
     r[0] = r[1] = r[2] = 0.0;
-    for (int i = 0; i < J.nmax; ++i) {
-        const int64_t k = ((int64_t)p * J.nmax + i) * J.n_joints + j;
-        const double s = J.sv[k];
-        if (s == 0.0) continue;
-        const int64_t g = J.ids[k];
+    for (int i0 = 0; i0 < J.nmax; i0 += kSlotBatch) {
+        double s[kSlotBatch], v[kSlotBatch][3];
+        int32_t g[kSlotBatch];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) r[c] += s * q[c * J.n_nodes + g];
+        for (int u = 0; u < kSlotBatch; ++u) {
+            const int i = min(i0 + u, J.nmax - 1);
+            const int64_t k = ((int64_t)p * J.nmax + i) * J.n_joints + j;
+            s[u] = i0 + u < J.nmax ? J.sv[k] : 0.0;
+            g[u] = J.ids[k];
+        }
+#pragma unroll
+        for (int u = 0; u < kSlotBatch; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[u][c] = q[c * J.n_nodes + g[u]];
+#pragma unroll
+        for (int u = 0; u < kSlotBatch; ++u)
+            if (s[u] != 0.0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) r[c] += s[u] * v[u][c];
+            }
     }
 }
 
@@ -80,18 +100,36 @@ __global__ __launch_bounds__(256) void k_joints(DevJoints J, const double *__res
 }
 
 // out[node] (+)= sum over the node's entries of s * z[entry's point], in
-// entry order
+// entry order, kEntryBatch entries at a time with their loads in flight
+// together (entries past the node's last reread it and are not added)
+constexpr int kEntryBatch = 8;
+
 __global__ __launch_bounds__(256) void k_joint_scatter(DevJoints J, double *__restrict__ out, int accumulate)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= J.n_touched) return;
     const int64_t g = J.tnode[t];
+    const int64_t k0 = J.tptr[t], k1 = J.tptr[t + 1];
     double s[3] = {0.0, 0.0, 0.0};
-    for (int64_t k = J.tptr[t]; k < J.tptr[t + 1]; ++k) {
-        const double *zr = J.z + 3 * J.tent[k];            // row 5 j + p
-        const double v = J.tval[k];
+    for (int64_t kb = k0; kb < k1; kb += kEntryBatch) {
+        int64_t e[kEntryBatch];
+        double v[kEntryBatch], z[kEntryBatch][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) s[c] += v * zr[c];
+        for (int u = 0; u < kEntryBatch; ++u) {
+            const int64_t k = kb + u < k1 ? kb + u : k1 - 1;
+            e[u] = J.tent[k];                                // row 5 j + p
+            v[u] = J.tval[k];
+        }
+#pragma unroll
+        for (int u = 0; u < kEntryBatch; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) z[u][c] = J.z[3 * e[u] + c];
+#pragma unroll
+        for (int u = 0; u < kEntryBatch; ++u)
+            if (kb + u < k1) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s[c] += v[u] * z[u][c];
+            }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
