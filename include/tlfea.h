@@ -254,7 +254,8 @@ typedef struct {
 
 /* Doubles of device workspace tlfea_newton_step needs for a basis of
  * `restart` vectors: (restart + 5) * 3 n_nodes + 8192 * ceil((restart + 1) / 8)
- * (the basis, four work vectors, and the dot-product partial sums). */
+ * + 4 (restart + 1) + 8 (the basis, four work vectors, the dot-product
+ * partial sums, and one iteration's scalars). */
 tlfea_status tlfea_newton_workspace(const tlfea_mesh *mesh, int32_t restart, int64_t *n_doubles);
 
 /*

@@ -52,6 +52,9 @@ hipError_t scratch_address(double **out);
 hipError_t launch_mdot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *partial,
                        hipStream_t s);
 hipError_t launch_maxpy(const double *V, int64_t ldv, int nvec, const double *c, double *y, int64_t n, hipStream_t s);
+hipError_t launch_cgs(int mode, const double *V, int64_t ldv, int nv, const double *c, double *w, int64_t n,
+                      double *partial, hipStream_t s);
+hipError_t launch_sum_partials(const double *partial, int nvec, double *out, double *neg, hipStream_t s);
 hipError_t launch_axpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t s);
 hipError_t launch_add(const double *x, const double *y, double *z, int64_t n, hipStream_t s);
 // joint kernels (tlfea_joints.hip)
@@ -1451,12 +1454,16 @@ extern "C" tlfea_status tlfea_newton_operator(tlfea_mesh *m, const double *q_n, 
 
 // Workspace layout of tlfea_newton_step (doubles): the Krylov basis
 // V_0..V_m, then w, x (the increment), b (= -g) and r, each 3 n_nodes long,
-// then the dot-product partial sums.
+// then the dot-product partial sums, then the device copies of one
+// iteration's scalars (two sets of projections, the squared norm, and the
+// two sets of negated projections).
+static int64_t newton_scalar_doubles(int restart) { return 4 * (int64_t)(restart + 1) + 8; }
+
 static int64_t newton_workspace_doubles(const tlfea_mesh *m, int restart)
 {
     const int64_t N = 3 * m->n_nodes;
     const int64_t chunks = (restart + 1 + kVecChunk - 1) / kVecChunk;
-    return (int64_t)(restart + 5) * N + (int64_t)kDotBlocks * kVecChunk * chunks;
+    return (int64_t)(restart + 5) * N + (int64_t)kDotBlocks * kVecChunk * chunks + newton_scalar_doubles(restart);
 }
 
 extern "C" tlfea_status tlfea_newton_workspace(const tlfea_mesh *m, int32_t restart, int64_t *n_doubles)
@@ -1565,6 +1572,13 @@ extern "C" tlfea_status tlfea_newton_step(tlfea_mesh *m, const double *q_n, cons
     const int64_t N = 3 * m->n_nodes;
     double *V = work, *w = work + (int64_t)(restart + 1) * N, *x = w + N, *b = x + N, *r = b + N;
     Krylov K{m, s, N, r + N, {}};
+    // this iteration's scalars on the device: projections of the two
+    // sweeps (ha, hb), the squared norm (nn, beside them for one copy), and
+    // the negated projections the next sweep adds (ca, cb)
+    const int64_t R1 = restart + 1;
+    double *ha = K.partial + (int64_t)kDotBlocks * kVecChunk * ((R1 + kVecChunk - 1) / kVecChunk);
+    double *hb = ha + R1, *nn = hb + R1, *ca = nn + 8, *cb = ca + R1;
+    std::vector<double> hs((size_t)(2 * R1 + 1));
     CallArgs rc{};
     rc.v = v; rc.qn = q_n; rc.vn = v_n; rc.h = h; rc.theta = theta; rc.sub = f_ext; rc.out0 = b;
     if ((st = enqueue(m, m->dm, kKRes, rc, s, false))) return st;      // b = g(v)
@@ -1594,17 +1608,37 @@ extern "C" tlfea_status tlfea_newton_step(tlfea_mesh *m, const double *q_n, cons
             double *Vj = V + (int64_t)j * N;
             if ((st = apply(Vj, w))) return st;
             // classical Gram-Schmidt, twice
-            if ((st = K.dots(V, j + 1, w, hc.data()))) return st;
-            for (int i = 0; i <= j; ++i) hc2[i] = -hc[i];
-            if ((st = K.combine(V, j + 1, hc2.data(), w))) return st;
-            if ((st = K.dots(V, j + 1, w, hc2.data()))) return st;
-            for (int i = 0; i <= j; ++i) {
-                hc[i] += hc2[i];
-                hc2[i] = -hc2[i];
-            }
-            if ((st = K.combine(V, j + 1, hc2.data(), w))) return st;
             double hn = 0.0;
-            if ((st = K.norm(w, &hn))) return st;
+            if (j + 1 <= kCgsMax) {
+                // three sweeps over the basis (projections; first update and
+                // second projections; second update and norm) with the
+                // scalars between them summed on the device, then one copy
+                // and one synchronisation; the same operations in the same
+                // order as the path below
+                const int nv = j + 1;
+                hipError_t e = launch_cgs(0, V, N, nv, nullptr, w, N, K.partial, s);
+                if (e == hipSuccess) e = launch_sum_partials(K.partial, nv, ha, ca, s);
+                if (e == hipSuccess) e = launch_cgs(1, V, N, nv, ca, w, N, K.partial, s);
+                if (e == hipSuccess) e = launch_sum_partials(K.partial, nv, hb, cb, s);
+                if (e == hipSuccess) e = launch_cgs(2, V, N, nv, cb, w, N, K.partial, s);
+                if (e == hipSuccess) e = launch_sum_partials(K.partial, 1, nn, nullptr, s);
+                if (e != hipSuccess) return fail(TLFEA_E_DEVICE, "Gram-Schmidt kernels: %s", hipGetErrorString(e));
+                HIP_TRY(hipMemcpyAsync(hs.data(), ha, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                for (int i = 0; i <= j; ++i) hc[i] = hs[i] + hs[(size_t)R1 + i];
+                hn = std::sqrt(hs[(size_t)2 * R1]);
+            } else {
+                if ((st = K.dots(V, j + 1, w, hc.data()))) return st;
+                for (int i = 0; i <= j; ++i) hc2[i] = -hc[i];
+                if ((st = K.combine(V, j + 1, hc2.data(), w))) return st;
+                if ((st = K.dots(V, j + 1, w, hc2.data()))) return st;
+                for (int i = 0; i <= j; ++i) {
+                    hc[i] += hc2[i];
+                    hc2[i] = -hc2[i];
+                }
+                if ((st = K.combine(V, j + 1, hc2.data(), w))) return st;
+                if ((st = K.norm(w, &hn))) return st;
+            }
             // the new column, rotated by the previous Givens rotations
             for (int i = 0; i <= j; ++i) H[(size_t)i * restart + j] = hc[i];
             for (int i = 0; i < j; ++i) {

@@ -92,6 +92,9 @@ enum { kOpMass = 3 };
 // launch of the multi-vector kernels.
 constexpr int kDotBlocks = 1024;
 constexpr int kVecChunk = 8;
+// Basis vectors the fused Gram-Schmidt sweeps take in one pass (larger
+// bases use the chunked dot and combination kernels).
+constexpr int kCgsMax = 32;
 
 // The no-allocation forward keeps its shared-node partial sums (three rows
 // of n_part doubles) in a static device array of this many doubles (64 MiB).

@@ -76,7 +76,110 @@ __global__ __launch_bounds__(256) void k_add(const double *__restrict__ x, const
     z[i] = x[i] + y[i];
 }
 
+// One sweep of classical Gram-Schmidt over V_0..V_{NV-1} (NV <= kCgsMax)
+// and the work vector w, block b of kDotBlocks taking the entries of
+// k_mdot's partition in the same order:
+//   MODE 0: partial[k][b] = V_k . w                 (the first projections)
+//   MODE 1: w += sum_k c_k V_k, then partial[k][b] = V_k . w   (the first
+//           update fused with the second projections)
+//   MODE 2: w += sum_k c_k V_k, then partial[0][b] = w . w     (the second
+//           update fused with the norm)
+// c is a device array (the negated projections, so that no host round trip
+// sits between the sweeps).  Every multiply-add and every block sum is the
+// one k_maxpy and k_mdot do, in the same order, so the results equal
+// theirs bit for bit; the basis is read three times per iteration instead
+// of four.
+template <int MODE, int NV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cgs(const double *__restrict__ V, int64_t ldv,
+                                             const double *__restrict__ c, double *__restrict__ w, int64_t n,
+                                             double *__restrict__ partial)
+{
+    constexpr int NS = MODE == 2 ? 1 : NV;
+    __shared__ double red[256];
+    double s[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s[k] = 0.0;
+    double ck[MODE >= 1 ? NV : 1];
+    if constexpr (MODE >= 1) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) ck[k] = c[k];
+    }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)256 * kDotBlocks) {
+        double v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = V[k * ldv + i];
+        double wi = w[i];
+        if constexpr (MODE >= 1) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) wi += ck[k] * v[k];
+            w[i] = wi;
+        }
+        if constexpr (MODE <= 1) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) s[k] += v[k] * wi;
+        } else {
+            s[0] += wi * wi;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        red[threadIdx.x] = s[k];
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[k * kDotBlocks + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+template <int MODE, int NV = 1>
+static hipError_t cgs_dispatch(int nv, const double *V, int64_t ldv, const double *c, double *w, int64_t n,
+                               double *partial, hipStream_t s)
+{
+    if constexpr (NV > kCgsMax) {
+        return hipErrorInvalidValue;
+    } else {
+        if (nv != NV) return cgs_dispatch<MODE, NV + 1>(nv, V, ldv, c, w, n, partial, s);
+        k_cgs<MODE, NV><<<kDotBlocks, 256, 0, s>>>(V, ldv, c, w, n, partial);
+        return hipGetLastError();
+    }
+}
+
+// out[k] = sum of vector k's block partials in block order (the host's
+// order), neg[k] = -out[k] when neg is given
+__global__ __launch_bounds__(64) void k_sum_partials(const double *__restrict__ partial, int nvec,
+                                                     double *__restrict__ out, double *__restrict__ neg)
+{
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= nvec) return;
+    double t = 0.0;
+    for (int b = 0; b < kDotBlocks; ++b) t += partial[(int64_t)k * kDotBlocks + b];
+    out[k] = t;
+    if (neg) neg[k] = -t;
+}
+
 static dim3 grid_of(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_cgs(int mode, const double *V, int64_t ldv, int nv, const double *c, double *w, int64_t n,
+                      double *partial, hipStream_t s)
+{
+    if (nv < 1 || nv > kCgsMax) return hipErrorInvalidValue;
+    switch (mode) {
+    case 0: return cgs_dispatch<0>(nv, V, ldv, c, w, n, partial, s);
+    case 1: return cgs_dispatch<1>(nv, V, ldv, c, w, n, partial, s);
+    case 2: return cgs_dispatch<2>(nv, V, ldv, c, w, n, partial, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sum_partials(const double *partial, int nvec, double *out, double *neg, hipStream_t s)
+{
+    if (nvec <= 0) return hipSuccess;
+    k_sum_partials<<<dim3((unsigned)((nvec + 63) / 64)), 64, 0, s>>>(partial, nvec, out, neg);
+    return hipGetLastError();
+}
 
 hipError_t launch_mdot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *partial,
                        hipStream_t s)
