@@ -148,14 +148,20 @@ static hipError_t cgs_dispatch(int nv, const double *V, int64_t ldv, const doubl
 }
 
 // out[k] = sum of vector k's block partials in block order (the host's
-// order), neg[k] = -out[k] when neg is given
-__global__ __launch_bounds__(64) void k_sum_partials(const double *__restrict__ partial, int nvec,
-                                                     double *__restrict__ out, double *__restrict__ neg)
+// order), neg[k] = -out[k] when neg is given.  One block per vector stages
+// the partials in LDS with all its threads (one round trip) and its first
+// thread adds them in order: a single thread loading them one by one waited
+// on every load (25 us per call).
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ partial, double *__restrict__ out,
+                                                      double *__restrict__ neg)
 {
-    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (k >= nvec) return;
+    __shared__ double p[kDotBlocks];
+    const int k = blockIdx.x;
+    for (int b = threadIdx.x; b < kDotBlocks; b += 256) p[b] = partial[(int64_t)k * kDotBlocks + b];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     double t = 0.0;
-    for (int b = 0; b < kDotBlocks; ++b) t += partial[(int64_t)k * kDotBlocks + b];
+    for (int b = 0; b < kDotBlocks; ++b) t += p[b];
     out[k] = t;
     if (neg) neg[k] = -t;
 }
@@ -177,7 +183,7 @@ hipError_t launch_cgs(int mode, const double *V, int64_t ldv, int nv, const doub
 hipError_t launch_sum_partials(const double *partial, int nvec, double *out, double *neg, hipStream_t s)
 {
     if (nvec <= 0) return hipSuccess;
-    k_sum_partials<<<dim3((unsigned)((nvec + 63) / 64)), 64, 0, s>>>(partial, nvec, out, neg);
+    k_sum_partials<<<dim3((unsigned)nvec), 256, 0, s>>>(partial, out, neg);
     return hipGetLastError();
 }
 
