@@ -34,6 +34,11 @@ hipError_t launch_mdot(const double *, int64_t, int, const double *, int64_t, do
 hipError_t launch_maxpy(const double *, int64_t, int, const double *, double *, int64_t, hipStream_t)
 { return hipErrorInvalidValue; }
 hipError_t launch_axpby(double, const double *, double, double *, int64_t, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_cgs(int, const double *, int64_t, int, const double *, double *, int64_t, double *, hipStream_t)
+{
+    return hipErrorInvalidValue;
+}
+hipError_t launch_sum_partials(const double *, int, double *, double *, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_add(const double *, const double *, double *, int64_t, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_joints(const DevJoints &, const double *, const double *, double, double, double *, int, hipStream_t)
 { return hipErrorInvalidValue; }
