@@ -312,7 +312,9 @@ tlfea_status tlfea_create_joints(int64_t n_nodes, const double *X_ref, int32_t n
 void tlfea_destroy_joints(tlfea_joints *joints);
 
 /* Row-normalised constraint values c_hat at positions q (DEVICE [3][n_nodes]);
- * c: DEVICE [n_joints][5], overwritten. */
+ * c: DEVICE [n_joints][5], overwritten.  The call copies q node-major into
+ * the joint set's device scratch (3 n_nodes doubles, allocated with the
+ * set): calls on one joint set must not overlap in time. */
 tlfea_status tlfea_joint_values(tlfea_joints *joints, const double *q, double *c, void *stream);
 
 /*

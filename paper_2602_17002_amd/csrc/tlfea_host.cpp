@@ -2094,6 +2094,16 @@ extern "C" tlfea_status tlfea_create_joints(int64_t n_nodes, const double *X, in
                 d.z = static_cast<double *>(p);
             }
         }
+        if (!st && nj > 0 && n_nodes > 0) {
+            // node-major copy of each call's positions (the point gathers)
+            void *p = nullptr;
+            hipError_t e = hipMalloc(&p, sizeof(double) * 3 * (size_t)n_nodes);
+            if (e != hipSuccess) st = fail(TLFEA_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+            else {
+                J->allocations.push_back(p);
+                d.qn = static_cast<double *>(p);
+            }
+        }
     }
     if (!st) {
         const hipError_t e = hipStreamSynchronize(s);

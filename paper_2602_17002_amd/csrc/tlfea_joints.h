@@ -13,6 +13,8 @@ struct DevJoints {
     const double *fw;         // [4][n_joints]: f_1, f_2 (a_0.b_10, a_0.b_20), DP1 row weights w_4, w_5
     double *z;                // [n_joints][5][3] the vector each point receives (scratch;
                               // joint-major, so an entry's three components share a line)
+    double *qn;               // [n_nodes][3] node-major copy of the positions of a call
+                              // (scratch: a gathered node's three coordinates share a line)
     const int32_t *tnode;     // [n_touched] nodes that receive joint forces
     const int64_t *tptr;      // [n_touched + 1] entry ranges
     const int64_t *tent;      // [entries] the entry's row of z: 5 j + p (joint j, point p)

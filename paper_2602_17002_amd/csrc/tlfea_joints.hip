@@ -16,14 +16,16 @@
 namespace tlfea {
 
 // r of point p of joint j: sum over the hosting element's nodes, in slot
-// order.  The slots are read kSlotBatch at a time with every load of a batch
-// in flight together (slot by slot, each slot waited for its shape value and
-// node id, then for the node's coordinates: two dependent round trips per
-// slot); slots past nmax reread the last one and unused slots (shape value 0,
-// node 0) are not added.
+// order, from the node-major copy qn of the positions (one cache line per
+// gathered node instead of one per coordinate array).  The slots are read
+// kSlotBatch at a time with every load of a batch in flight together (slot
+// by slot, each slot waited for its shape value and node id, then for the
+// node's coordinates: two dependent round trips per slot); slots past nmax
+// reread the last one and unused slots (shape value 0, node 0) are not
+// added.
 constexpr int kSlotBatch = 10;
 
-__device__ __forceinline__ void point_eval(const DevJoints &J, const double *__restrict__ q, int p, int64_t j,
+__device__ __forceinline__ void point_eval(const DevJoints &J, const double *__restrict__ qn, int p, int64_t j,
                                            double r[3])
 {
     r[0] = r[1] = r[2] = 0.0;
@@ -40,7 +42,7 @@ __device__ __forceinline__ void point_eval(const DevJoints &J, const double *__r
 #pragma unroll
         for (int u = 0; u < kSlotBatch; ++u)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) v[u][c] = q[c * J.n_nodes + g[u]];
+            for (int c = 0; c < 3; ++c) v[u][c] = qn[3 * (int64_t)g[u] + c];
 #pragma unroll
         for (int u = 0; u < kSlotBatch; ++u)
             if (s[u] != 0.0) {
@@ -54,7 +56,16 @@ __device__ __forceinline__ double dot3(const double *a, const double *b) { retur
 
 // c_hat (n_joints x 5, joint-major) and, when z is wanted, the vector each
 // point receives: z_X = h sum_k w_k eta_k dc_k/dr_X, eta = lambda + rho c_hat.
-__global__ __launch_bounds__(256) void k_joints(DevJoints J, const double *__restrict__ q,
+// qn[g][c] = q[c][g]: the caller's [3][n_nodes] positions node-major
+__global__ __launch_bounds__(256) void k_node_major(const double *__restrict__ q, double *__restrict__ qn, int64_t n)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) qn[3 * g + c] = q[c * n + g];
+}
+
+__global__ __launch_bounds__(256) void k_joints(DevJoints J, const double *__restrict__ qn,
                                                 const double *__restrict__ lambda, double rho, double h,
                                                 double *__restrict__ c_out, int want_z)
 {
@@ -62,7 +73,7 @@ __global__ __launch_bounds__(256) void k_joints(DevJoints J, const double *__res
     if (j >= J.n_joints) return;
     double r[5][3];
 #pragma unroll
-    for (int p = 0; p < 5; ++p) point_eval(J, q, p, j, r[p]);
+    for (int p = 0; p < 5; ++p) point_eval(J, qn, p, j, r[p]);
     double a[3], b1[3], b2[3], d[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -148,7 +159,10 @@ hipError_t launch_joints(const DevJoints &J, const double *q, const double *lamb
                          double *c_out, int want_z, hipStream_t s)
 {
     if (J.n_joints <= 0) return hipSuccess;
-    k_joints<<<dim3((unsigned)((J.n_joints + 255) / 256)), 256, 0, s>>>(J, q, lambda, rho, h, c_out, want_z);
+    k_node_major<<<dim3((unsigned)((J.n_nodes + 255) / 256)), 256, 0, s>>>(q, J.qn, J.n_nodes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_joints<<<dim3((unsigned)((J.n_joints + 255) / 256)), 256, 0, s>>>(J, J.qn, lambda, rho, h, c_out, want_z);
     return hipGetLastError();
 }
 
