@@ -157,6 +157,36 @@ __device__ __forceinline__ double det_from_cof(const m3 &A, const m3 &C)
     return A[0][0] * C[0][0] + A[0][1] * C[0][1] + A[0][2] * C[0][2];
 }
 
+// 1 / d for a normal, nonzero d: the hardware estimate refined by two Newton
+// steps r <- r + r (1 - d r), each of which squares the relative error; the
+// result is within two units in the last place of the quotient (five
+// instructions in place of the eleven of a correctly rounded division).
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+// J^(-1/3) with the sign of J, for |J| in the normal single-precision range:
+// a single-precision estimate exp2(-log2|J| / 3) (relative error about
+// 1e-7), then two Newton steps y <- y + y (1 - |J| y^3) / 3 in double, each
+// of which takes a relative error e to about 2 e^2; within two units in the
+// last place.
+__device__ __forceinline__ double inv_cbrt(double J)
+{
+    const double a = fabs(J);
+    double y = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf((float)a) * (1.0f / 3.0f));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-a, y * y * y, 1.0);
+        y = fma(y * e, 1.0 / 3.0, y);
+    }
+    return copysign(y, J);
+}
+
 struct Mat {
     double p0, p1, p2, mu_v, lam_v;
 };
@@ -360,7 +390,7 @@ __device__ __forceinline__ void finish_last_node(double (&out)[NEN][3])
 // K = cof(J) = J_p J^{-T} and r = 1 / J_p; REL as for grad_field.  Evaluated at every point from
 // all nodes: straight-sided elements have a constant J only up to the
 // rounding of their mid-edge coordinates, which the bulk response amplifies.
-template <int ELEM, int NEN, bool REL = false, class QT>
+template <int ELEM, int NEN, bool REL = false, bool FAST = false, class QT>
 __device__ __forceinline__ void ref_geometry(QT q, const double *__restrict__ sX, const int (&na)[NEN], m3 &K,
                                              double &detJ, double &r)
 {
@@ -368,7 +398,8 @@ __device__ __forceinline__ void ref_geometry(QT q, const double *__restrict__ sX
     grad_field<ELEM, NEN, REL>(q, sX, na, J);
     cofactor(J, K);
     detJ = det_from_cof(J, K);
-    r = 1.0 / detJ;
+    if constexpr (FAST) r = recip(detJ);
+    else r = 1.0 / detJ;
 }
 
 // A = G J^{-1} = (G K^T) r: the gradient with respect to the reference
@@ -472,25 +503,26 @@ __device__ __forceinline__ void acc_mul_ms(const m3 &M, const s3 &S, m3 &R)
 // Invariants and pieces shared by the Mooney-Rivlin stress and its derivative.
 struct MRState {
     m3 FiT;          // F^{-T}
-    double J, J23, I1;
+    m3 cof;          // cof F = J F^{-T} (the forward's Neo-Hookean stress uses it
+                     // with 1/J folded into its scalar coefficient)
+    double J, invJ, J23, I1;
     // Mooney-Rivlin (mu01) only
     m3 C, FC;
     double J43, I2;
 };
 
-template <int LAW>
+template <int LAW, bool FAST = false>
 __device__ __forceinline__ void mr_state(const m3 &F, MRState &st)
 {
-    m3 cof;
-    cofactor(F, cof);
-    st.J = det_from_cof(F, cof);
-    const double invJ = 1.0 / st.J;
+    cofactor(F, st.cof);
+    st.J = det_from_cof(F, st.cof);
+    st.invJ = FAST ? recip(st.J) : 1.0 / st.J;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) st.FiT[i][j] = cof[i][j] * invJ;
-    const double c = cbrt(invJ);          // J^{-1/3}
-    st.J23 = c * c;                       // J^{-2/3}
+        for (int j = 0; j < 3; ++j) st.FiT[i][j] = st.cof[i][j] * st.invJ;
+    const double c = FAST ? inv_cbrt(st.J) : cbrt(st.invJ);   // J^{-1/3}
+    st.J23 = c * c;                                           // J^{-2/3}
     st.I1 = ddot(F, F);                   // tr C
     if constexpr (LAW == 1) {
         mTm(F, F, st.C);
@@ -505,7 +537,7 @@ __device__ __forceinline__ void mr_state(const m3 &F, MRState &st)
 //   MR : P = 2 mu10 J^{-2/3}(F - I1/3 F^{-T}) + 2 mu01 J^{-4/3}(I1 F - F C - 2/3 I2 F^{-T})
 //          + k (J-1) J F^{-T};  NH is MR with mu01 = 0.
 // With Kelvin-Voigt the viscous S_v(Edot) is added (P = F (S + S_v) for SVK).
-template <int LAW, bool DAMPED>
+template <int LAW, bool DAMPED, bool FAST = false>
 __device__ __forceinline__ void stress(const m3 &F, const m3 &Fd, const Mat &m, m3 &P)
 {
     if constexpr (LAW == 0) {
@@ -528,13 +560,22 @@ __device__ __forceinline__ void stress(const m3 &F, const m3 &Fd, const Mat &m, 
         mm(F, S, P);
     } else {
         MRState st;
-        mr_state<LAW>(F, st);
+        mr_state<LAW, FAST>(F, st);
         const double a = 2.0 * m.p0 * st.J23;
-        const double b = -(2.0 / 3.0) * m.p0 * st.J23 * st.I1 + m.p2 * (st.J - 1.0) * st.J;
+        if constexpr (LAW == 2 && FAST) {
+            // b F^{-T} = (b / J) cof F, with k (J - 1) J / J = k (J - 1)
+            const double b = -(2.0 / 3.0) * m.p0 * st.J23 * st.I1 * st.invJ + m.p2 * (st.J - 1.0);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) P[i][j] = a * F[i][j] + b * st.FiT[i][j];
+                for (int j = 0; j < 3; ++j) P[i][j] = a * F[i][j] + b * st.cof[i][j];
+        } else {
+            const double b = -(2.0 / 3.0) * m.p0 * st.J23 * st.I1 + m.p2 * (st.J - 1.0) * st.J;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) P[i][j] = a * F[i][j] + b * st.FiT[i][j];
+        }
         if constexpr (LAW == 1) {
             const double be = 2.0 * m.p1 * st.J43;
 #pragma unroll
@@ -741,18 +782,19 @@ __device__ __forceinline__ void fwd_element(const double *sm, const int (&na)[NE
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpFwd, DAMPED, MODE>;
+    constexpr bool FAST = ELEM != kQ27;
     for_points<ELEM>(part, [&](auto q) {
         qp_fence();
         m3 K, G, F, Fd, P, Qm;
         double detJ, r;
-        ref_geometry<ELEM, NEN, true>(q, sm + R::oX, na, K, detJ, r);
+        ref_geometry<ELEM, NEN, true, FAST>(q, sm + R::oX, na, K, detJ, r);
         grad_field<ELEM, NEN, true>(q, sm + R::ox, na, G);
         to_reference(G, K, r, F);                   // F = N H
         if constexpr (DAMPED) {
             grad_field<ELEM, NEN>(q, sm + R::ov, na, G);
             to_reference(G, K, r, Fd);              // Fdot = Ndot H
         }
-        stress<LAW, DAMPED>(F, Fd, mt, P);
+        stress<LAW, DAMPED, FAST>(F, Fd, mt, P);
         to_parent(P, K, weight_at<ELEM>(q), Qm);
         scatter_grad<ELEM, NEN>(q, Qm, fe);
     });
@@ -779,10 +821,11 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
     // first node there.  The H8 adjoint keeps tile-relative positions (with
     // them its schedule spills hundreds of registers).
     constexpr bool REL = WANT_GT && ELEM == kT10;
+    constexpr bool FAST = ELEM != kQ27 && !WANT_GT;
     for_points<ELEM>(part, [&](auto q) {
         m3 K, G, F, Gw, Fb;
         double detJ, r;
-        ref_geometry<ELEM, NEN, REL>(q, sm + R::oX, na, K, detJ, r);
+        ref_geometry<ELEM, NEN, REL, FAST>(q, sm + R::oX, na, K, detJ, r);
         grad_field<ELEM, NEN, REL>(q, sm + R::ox, na, G);
         to_reference(G, K, r, F);
         grad_field<ELEM, NEN>(q, sm + R::o2, na, G);
@@ -821,7 +864,7 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
             }
         }
         MRState st;
-        if constexpr (LAW != 0) mr_state<LAW>(F, st);
+        if constexpr (LAW != 0) mr_state<LAW, FAST>(F, st);
         DerivScalars ds;
         delastic_acc<LAW>(F, mt, Gw, st, Fb, ds);
         if constexpr (WANT_GT) {
