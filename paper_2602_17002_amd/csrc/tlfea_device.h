@@ -905,18 +905,19 @@ __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NE
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpJvp, DAMPED>;
+    constexpr bool FAST = ELEM != kQ27 && !DT && LAW != 1;
     for_points<ELEM>(part, [&](auto q) {
         qp_fence();
         m3 K, G, F, dF, dP;
         double detJ, r;
-        ref_geometry<ELEM, NEN>(q, sm + R::oX, na, K, detJ, r);
+        ref_geometry<ELEM, NEN, false, FAST>(q, sm + R::oX, na, K, detJ, r);
         grad_field<ELEM, NEN>(q, sm + R::ox, na, G);
         to_reference(G, K, r, F);
         grad_field<ELEM, NEN>(q, sm + R::o2, na, G);
         to_reference(G, K, r, dF);
         {
             MRState st;
-            if constexpr (LAW != 0) mr_state<LAW>(F, st);
+            if constexpr (LAW != 0) mr_state<LAW, FAST>(F, st);
             delastic<LAW>(F, mt, dF, st, dP);
         }
         if constexpr (DAMPED) {
