@@ -387,7 +387,8 @@ __device__ __forceinline__ void finish_last_node(double (&out)[NEN][3])
 }
 
 // Reference geometry at point Q (Sec. 6): J = U dS/dxi, J_p = det J,
-// K = cof(J) = J_p J^{-T} and r = 1 / J_p; REL as for grad_field.  Evaluated at every point from
+// K = cof(J) = J_p J^{-T} and r = 1 / J_p (FAST: by recip); REL as for
+// grad_field.  Evaluated at every point from
 // all nodes: straight-sided elements have a constant J only up to the
 // rounding of their mid-edge coordinates, which the bulk response amplifies.
 template <int ELEM, int NEN, bool REL = false, bool FAST = false, class QT>
@@ -511,6 +512,8 @@ struct MRState {
     double J43, I2;
 };
 
+// FAST: 1/J and J^(-1/3) by recip and inv_cbrt instead of a division and
+// the library cube root.
 template <int LAW, bool FAST = false>
 __device__ __forceinline__ void mr_state(const m3 &F, MRState &st)
 {
@@ -537,6 +540,7 @@ __device__ __forceinline__ void mr_state(const m3 &F, MRState &st)
 //   MR : P = 2 mu10 J^{-2/3}(F - I1/3 F^{-T}) + 2 mu01 J^{-4/3}(I1 F - F C - 2/3 I2 F^{-T})
 //          + k (J-1) J F^{-T};  NH is MR with mu01 = 0.
 // With Kelvin-Voigt the viscous S_v(Edot) is added (P = F (S + S_v) for SVK).
+// FAST: mr_state's FAST, and the Neo-Hookean F^{-T} term from cof F.
 template <int LAW, bool DAMPED, bool FAST = false>
 __device__ __forceinline__ void stress(const m3 &F, const m3 &Fd, const Mat &m, m3 &P)
 {
@@ -782,6 +786,8 @@ __device__ __forceinline__ void fwd_element(const double *sm, const int (&na)[NE
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpFwd, DAMPED, MODE>;
+    // the shorter reciprocal and cube root where they leave the register
+    // schedule as it was or better (measured per instantiation): not Q27
     constexpr bool FAST = ELEM != kQ27;
     for_points<ELEM>(part, [&](auto q) {
         qp_fence();
@@ -821,7 +827,7 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
     // first node there.  The H8 adjoint keeps tile-relative positions (with
     // them its schedule spills hundreds of registers).
     constexpr bool REL = WANT_GT && ELEM == kT10;
-    constexpr bool FAST = ELEM != kQ27 && !WANT_GT;
+    constexpr bool FAST = ELEM != kQ27 && !WANT_GT;   // as in fwd_element; not with gtheta
     for_points<ELEM>(part, [&](auto q) {
         m3 K, G, F, Gw, Fb;
         double detJ, r;
@@ -905,6 +911,7 @@ __device__ __forceinline__ void jvp_element(const double *sm, const int (&na)[NE
 {
     using E = ElemDef<ELEM>;
     using R = Rec<kOpJvp, DAMPED>;
+    // as in fwd_element; not with a parameter direction, not Mooney-Rivlin
     constexpr bool FAST = ELEM != kQ27 && !DT && LAW != 1;
     for_points<ELEM>(part, [&](auto q) {
         qp_fence();
