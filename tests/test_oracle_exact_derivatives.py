@@ -5,9 +5,11 @@ viscous stress F S_v(Edot) (Sec. 3.2.3), and the element force the rule's
 sum of w_q J_p P h_a (Sec. 4.3, 6).  A second level of dual numbers gives
 the tangent product K dx + C dv without differencing, and one such product
 per unit direction the whole element Jacobian, whose transpose applied to w
-is the adjoint.  Every element type (T10, H8, Q27) and every law (Saint
-Venant-Kirchhoff, Mooney-Rivlin, Neo-Hookean, with and without
-Kelvin-Voigt damping) on one curved element, offset by tens of element
+is the adjoint.  The consistent mass (Sec. 4.1) from its own transcription
+of each mass rule gives the step residual and, through the same dual
+numbers, the Newton operator (Sec. 7).  Every element type (T10, H8, Q27)
+and every law (Saint Venant-Kirchhoff, Mooney-Rivlin, Neo-Hookean, with and
+without Kelvin-Voigt damping) on one curved element, offset by tens of element
 sizes, under a rotation and strains of a few per cent.  60 digits leave
 the reference exact far below FP64 rounding, so what the bars measure is
 the oracle's own rounding.  The force is a difference of terms larger than
@@ -385,3 +387,142 @@ def test_adjoint_against_the_exact_element_jacobian(elem, lawname):
             assert rt[p, 0] == 0, (p, rt[p, 0])
         else:
             assert abs(rt[p, 0] - gt[p]) <= BAR * abs(gt[p]), (p, rt[p, 0], gt[p])
+
+
+# ------------------------------------------- inertia and the step (Sec. 4.1, 7)
+
+def mass_points(elem):
+    """(shape values, parent gradients, weight) at the points of the mass
+    rule.  T10: the 15-point degree-5 rule on the tetrahedron, barycentric
+    orbits the centroid (weight 16/135), (a, a, a, 1 - 3a) for
+    a = (7 -+ sqrt 15)/34 (weights (2665 +- 14 sqrt 15)/37800) and
+    (b, b, 1/2 - b, 1/2 - b) for b = (5 - sqrt 15)/20 (weight 10/189), all
+    times the volume 1/6.  H8 and Q27: their Gauss rules (as for the force)."""
+    r15 = D(15).sqrt()
+    if elem == O.T10:
+        _, bary = t10_rule()
+        bary = [[D(repr(t)) for t in row] for row in bary]
+        pts = [([D(1) / 4] * 4, D(16) / 135)]
+        for a, w in (((7 - r15) / 34, (2665 + 14 * r15) / 37800), ((7 + r15) / 34, (2665 - 14 * r15) / 37800)):
+            for m in range(4):
+                L = [a] * 4
+                L[m] = 1 - 3 * a
+                pts.append((L, w))
+        b = (5 - r15) / 20
+        for i in range(4):
+            for j in range(i + 1, 4):
+                L = [D(1) / 2 - b] * 4
+                L[i] = L[j] = b
+                pts.append((L, D(10) / 189))
+        dL = [(-1, -1, -1), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+        out = []
+        for L, w in pts:
+            s, G = [], []
+            for node in bary:
+                nz = [i for i in range(4) if node[i] != 0]
+                if len(nz) == 1:
+                    i = nz[0]
+                    s.append(L[i] * (2 * L[i] - 1))
+                    G.append([(4 * L[i] - 1) * dL[i][k] for k in range(3)])
+                else:
+                    i, j = nz
+                    s.append(4 * L[i] * L[j])
+                    G.append([4 * (L[i] * dL[j][k] + L[j] * dL[i][k]) for k in range(3)])
+            out.append((s, G, w / 6, L))
+        return out
+    rule, nodes = RULES[elem]()
+    out = []
+    if elem == O.H8:
+        g = 1 / D(3).sqrt()
+        pts = [(px, py, pz) for pz in (-g, g) for py in (-g, g) for px in (-g, g)]
+        for (G, w), p in zip(rule, pts):
+            s = [(1 + n[0] * p[0]) * (1 + n[1] * p[1]) * (1 + n[2] * p[2]) / 8 for n in nodes]
+            out.append((s, G, w, p))
+        return out
+    g = (D(3) / 5).sqrt()
+    gp = [-g, D(0), g]
+    ijk = [(n[0] + 1, n[1] + 1, n[2] + 1) for n in nodes]
+    lag = lambda t: [t * (t - 1) / 2, 1 - t * t, t * (t + 1) / 2]
+    pts = [(px, py, pz) for pz in gp for py in gp for px in gp]
+    for (G, w), p in zip(rule, pts):
+        Lx, Ly, Lz = lag(p[0]), lag(p[1]), lag(p[2])
+        s = [Lx[i] * Ly[j] * Lz[k] for i, j, k in ijk]
+        out.append((s, G, w, p))
+    return out
+
+
+def test_t10_mass_rule_is_exact_to_degree_five():
+    """The transcription of the 15-point rule used below integrates every
+    monomial of degree <= 5 over the unit tetrahedron exactly
+    (i! j! k! / (i + j + k + 3)!), which fixes its orbits and weights."""
+    from math import factorial
+    with decimal.localcontext(CTX):
+        pts = mass_points(O.T10)
+        assert len(pts) == 15
+        for i in range(6):
+            for j in range(6 - i):
+                for k in range(6 - i - j):
+                    q = sum((w * L[1] ** i * L[2] ** j * L[3] ** k for _, _, w, L in pts), D(0))
+                    ex = D(factorial(i) * factorial(j) * factorial(k)) / D(factorial(i + j + k + 3))
+                    assert abs(q - ex) < D("1e-50"), (i, j, k)
+
+
+def element_mass(elem, rho, X):
+    """m_ab = rho sum_q w_q s_a s_b det J_q (Sec. 4.1) with the mass rule."""
+    pts = mass_points(elem)
+    nen = len(pts[0][0])
+    M = [[D(0)] * nen for _ in range(nen)]
+    for s, G, w, _ in pts:
+        c = rho * w * det3(mat(X, G))
+        for a in range(nen):
+            for b in range(nen):
+                M[a][b] = M[a][b] + c * s[a] * s[b]
+    return M
+
+
+def step_residual(elem, law, th, damped, rho, X, qn, vn, v, h):
+    """g(v) = M (v - v_n) / h + f_int(q_n + h v, v) (Sec. 7, no constraints,
+    f_ext = 0)."""
+    nen = len(X[0])
+    x = [[qn[i][a] + h * v[i][a] for a in range(nen)] for i in range(3)]
+    f = element_force(elem, law, th, damped, X, x, v)
+    M = element_mass(elem, rho, X)
+    return [[f[a][i] + sum((M[a][b] * (v[i][b] - vn[i][b]) for b in range(nen)), D(0)) / h
+             for i in range(3)] for a in range(nen)]
+
+
+def grid(a, step):
+    return np.round(np.asarray(a) / step) * step
+
+
+@pytest.mark.parametrize("elem,lawname", [(O.T10, "MR+KV"), (O.H8, "NH"), (O.Q27, "SVK+KV")],
+                         ids=["T10-MR+KV", "H8-NH", "Q27-SVK+KV"])
+def test_step_residual_and_newton_operator_against_exact_evaluation(elem, lawname):
+    """The step residual against its 60-digit evaluation, and the Newton
+    operator (M/h + h K + C) dv against the exact derivative of that
+    evaluation along dv.  The inputs make q = q_n + h v, v - v_n and the
+    division by h exact in FP64 (h = 2^-13, q_n on a 2^-40 m grid, v and v_n
+    on a 2^-20 m/s grid), so both sides see the same positions."""
+    law, th, damped = LAWS[lawname]
+    X, x, _ = curved_element(elem, 90 + elem)
+    rng = np.random.default_rng(91 + elem)
+    h, rho = 2.0 ** -13, 1100.0
+    qn = grid(x, 2.0 ** -40)
+    v = grid(rng.normal(0, 0.3, X.shape), 2.0 ** -20)
+    vn = grid(v + rng.normal(0, 0.3, X.shape), 2.0 ** -20)
+    dv = rng.normal(0, 1.0, X.shape)
+    assert np.array_equal((qn + h * v) - h * v, qn)
+    blk = block(elem, law, th, damped)
+    blk.rho = rho
+    with decimal.localcontext(CTX):
+        thd = [dec(t) for t in th]
+        Xd, qd, vd, vnd, dvd = to_dec(X), to_dec(qn), to_dec(v), to_dec(vn), to_dec(dv)
+        hd, rd = dec(h), dec(rho)
+        g = as_array(step_residual(elem, law, thd, damped, rd, Xd, qd, vnd, vd, hd))
+        ve = [[Dual(vd[i][a], dvd[i][a]) for a in range(len(vd[0]))] for i in range(3)]
+        ge = step_residual(elem, law, thd, damped, rd, Xd, qd, vnd, ve, hd)
+        y = np.array([[float(eps(t)) for t in row] for row in ge]).T
+    got = O.step_residual(X, [blk], qn, vn, v, h)
+    assert rel(got, g) <= BAR, rel(got, g)
+    op = O.newton_operator(X, [blk], qn, v, h, dv)
+    assert rel(op, y) <= BAR, rel(op, y)
