@@ -7,7 +7,9 @@ the tangent product K dx + C dv without differencing, and one such product
 per unit direction the whole element Jacobian, whose transpose applied to w
 is the adjoint.  The consistent mass (Sec. 4.1) from its own transcription
 of each mass rule gives the step residual and, through the same dual
-numbers, the Newton operator (Sec. 7).  Every element type (T10, H8, Q27)
+numbers, the Newton operator (Sec. 7); the revolute joint's values and
+transpose scatter (Sec. 2.2, App. B.1) follow from its defining rows, the
+Jacobian again by exact differentiation.  Every element type (T10, H8, Q27)
 and every law (Saint Venant-Kirchhoff, Mooney-Rivlin, Neo-Hookean, with and
 without Kelvin-Voigt damping) on one curved element, offset by tens of element
 sizes, under a rotation and strains of a few per cent.  60 digits leave
@@ -32,6 +34,7 @@ D = decimal.Decimal
 CTX = decimal.Context(prec=60)
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 BAR = 2e-13
+JBAR = 1e-12
 
 
 class Dual:
@@ -526,3 +529,94 @@ def test_step_residual_and_newton_operator_against_exact_evaluation(elem, lawnam
     assert rel(got, g) <= BAR, rel(got, g)
     op = O.newton_operator(X, [blk], qn, v, h, dv)
     assert rel(op, y) <= BAR, rel(op, y)
+
+
+# ------------------------------------------------ the revolute joint (Sec. 2.2)
+
+def shape_exact(elem, xi):
+    """Shape values at parent point xi: T10 corner L_i (2 L_i - 1), mid-edge
+    4 L_i L_j with L = (1 - xi - eta - zeta, xi, eta, zeta); H8 trilinear;
+    Q27 products of the 1-D quadratic Lagrange polynomials."""
+    if elem == O.T10:
+        _, bary = t10_rule()
+        L = [1 - xi[0] - xi[1] - xi[2], xi[0], xi[1], xi[2]]
+        s = []
+        for node in bary:
+            nz = [i for i in range(4) if node[i] != 0]
+            s.append(L[nz[0]] * (2 * L[nz[0]] - 1) if len(nz) == 1 else 4 * L[nz[0]] * L[nz[1]])
+        return s
+    _, nodes = RULES[elem]()
+    if elem == O.H8:
+        return [(1 + n[0] * xi[0]) * (1 + n[1] * xi[1]) * (1 + n[2] * xi[2]) / 8 for n in nodes]
+    lag = lambda t: [t * (t - 1) / 2, 1 - t * t, t * (t + 1) / 2]
+    Lx, Ly, Lz = lag(xi[0]), lag(xi[1]), lag(xi[2])
+    return [Lx[n[0] + 1] * Ly[n[1] + 1] * Lz[n[2] + 1] for n in nodes]
+
+
+def joint_values_exact(Xd, qd, pts):
+    """Row-normalised revolute values W c (Sec. 2.2, App. B.1): c = (r_R - r_P,
+    a.b_1 - f_1, a.b_2 - f_2), a = r_Q - r_P, b_j = r_{S,T} - r_R, f_j and the
+    DP1 weights 1 / sqrt(|a_0|^2 + |b_j0|^2) from the reference positions."""
+    def positions(y):
+        r = {}
+        for key, (elem, nodes, xi) in pts.items():
+            s = shape_exact(elem, [dec(t) for t in xi])
+            r[key] = [sum((s[a] * y[i][n] for a, n in enumerate(nodes)), D(0)) for i in range(3)]
+        return r
+    dot = lambda u, v: u[0] * v[0] + u[1] * v[1] + u[2] * v[2]
+    sub = lambda u, v: [u[i] - v[i] for i in range(3)]
+    r0, r = positions(Xd), positions(qd)
+    a0, b10, b20 = sub(r0["Q"], r0["P"]), sub(r0["S"], r0["R"]), sub(r0["T"], r0["R"])
+    a, b1, b2 = sub(r["Q"], r["P"]), sub(r["S"], r["R"]), sub(r["T"], r["R"])
+    w1 = 1 / (dot(a0, a0) + dot(b10, b10)).sqrt()
+    w2 = 1 / (dot(a0, a0) + dot(b20, b20)).sqrt()
+    d = sub(r["R"], r["P"])
+    return [d[0], d[1], d[2], w1 * (dot(a, b1) - dot(a0, b10)), w2 * (dot(a, b2) - dot(a0, b20))]
+
+
+def test_revolute_joint_values_and_scatter_against_exact_evaluation():
+    """The five points in elements of all three types, a configuration that
+    violates the joint by about a millimetre: values against the 60-digit
+    evaluation, and the scatter h C^T (lambda + rho c) with each column of
+    C the exact derivative of the values along one nodal coordinate.  The
+    rows are differences of point positions some 50 times longer than the
+    fibres between them, and the DP1 rows products of two such differences
+    less their reference value (a condition of 10^3-10^4), so FP64 gives
+    them to 1e-13-1e-12: the bar here is JBAR = 1e-12.  The mistakes this
+    is meant to catch (a wrong weight, sign, block or factor) move them by
+    0.1 or more."""
+    rng = np.random.default_rng(95)
+    nodes_of = {}
+    X = np.zeros((3, 0))
+    for elem, seed in ((O.T10, 96), (O.H8, 97), (O.Q27, 98)):
+        Xe, _, _ = curved_element(elem, seed)
+        nodes_of[elem] = list(range(X.shape[1], X.shape[1] + Xe.shape[1]))
+        X = np.hstack([X, Xe])
+    c, s = np.cos(0.2), np.sin(0.2)
+    R = np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+    q = R @ X + rng.normal(0, 1e-3, X.shape)
+    t10_xi = lambda: (lambda u: u / (u.sum() + rng.uniform(0.2, 1.0)))(rng.uniform(0.05, 1.0, 3))
+    cube_xi = lambda: rng.uniform(-0.9, 0.9, 3)
+    pts = {"P": (O.T10, nodes_of[O.T10], t10_xi()), "Q": (O.H8, nodes_of[O.H8], cube_xi()),
+           "R": (O.Q27, nodes_of[O.Q27], cube_xi()), "S": (O.T10, nodes_of[O.T10], t10_xi()),
+           "T": (O.H8, nodes_of[O.H8], cube_xi())}
+    lam = rng.normal(0, 1, 5)
+    rho, h = 1e4, 1e-3
+    n = X.shape[1]
+    with decimal.localcontext(CTX):
+        Xd, qd = to_dec(X), to_dec(q)
+        cv = joint_values_exact(Xd, qd, pts)
+        eta = [dec(lam[k]) + dec(rho) * cv[k] for k in range(5)]
+        g = np.zeros((3, n))
+        for i in range(3):
+            for m in range(n):
+                qe = [[Dual(qd[r][a], 1 if (r, a) == (i, m) else 0) for a in range(n)] for r in range(3)]
+                col = joint_values_exact(Xd, qe, pts)
+                g[i, m] = float(dec(h) * sum((eta[k] * eps(col[k]) for k in range(5)), D(0)))
+        cvf = np.array([float(t) for t in cv])
+    from oracle import constraints as OC
+    joint = {k: (e, nd, xi) for k, (e, nd, xi) in pts.items()}
+    got = OC.revolute_values(X, q, [joint])[0]
+    assert rel(got, cvf) <= JBAR, rel(got, cvf)
+    gs = OC.revolute_scatter(X, q, [joint], lam, rho, h)
+    assert rel(gs, g) <= JBAR, rel(gs, g)
