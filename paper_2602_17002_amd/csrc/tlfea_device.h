@@ -827,7 +827,8 @@ __device__ __forceinline__ void vjp_element(const double *sm, const int (&na)[NE
     // first node there.  The H8 adjoint keeps tile-relative positions (with
     // them its schedule spills hundreds of registers).
     constexpr bool REL = WANT_GT && ELEM == kT10;
-    constexpr bool FAST = ELEM != kQ27 && !WANT_GT;   // as in fwd_element; not with gtheta
+    // as in fwd_element; not with gtheta on a damped block
+    constexpr bool FAST = ELEM != kQ27 && !(WANT_GT && DAMPED);
     for_points<ELEM>(part, [&](auto q) {
         m3 K, G, F, Gw, Fb;
         double detJ, r;
