@@ -189,6 +189,49 @@ def test_large_deformation(elem, law):
     assert rel(df, O.jvp(X, p.blocks, x, v, dx, dv)) <= TOL
 
 
+@pytest.mark.parametrize("damped", [False, True], ids=["undamped", "damped"])
+@pytest.mark.parametrize("law", ["SVK", "NH", "MR"])
+@pytest.mark.parametrize("elem", [synth.T10, synth.H8], ids=["T10", "H8"])
+def test_reflected_state(elem, law, damped):
+    # Every point inverted (a mirror image of a 10 % strain state, det F
+    # near -1, every |det F| far from zero): the stress laws are evaluated
+    # there as written (real cube roots of negative J), and every output,
+    # the adjoint with and without the parameter gradients, matches the
+    # oracle.
+    rng = np.random.default_rng(61)
+    lid, th = LAWS[law]
+    n = (6, 4, 3)
+    X, conn = (synth.box_t10 if elem == synth.T10 else synth.box_h8)(*n, size=tuple(0.02 * k for k in n))
+    x = synth.sinusoidal_state(X, 0.1, rng) * np.array([[1.0], [-1.0], [1.0]])
+    v = rng.normal(0, 1.0, X.shape) if damped else np.zeros_like(X)
+    t = th.copy() if damped else np.concatenate([th[:3], [0.0, 0.0]])
+    b = synth.Block(elem, lid, conn, t, damped=damped)
+    b.theta_e = t[:, None] * rng.uniform(0.5, 2.0, (5, conn.shape[0]))
+    p = synth.Problem(f"reflected-{synth.ELEM_NAMES[elem]}-{law}", X, x, v, [b], cell=0.02)
+    ninv, min_det = O.count_inverted(p.X, p.blocks, p.x)
+    assert ninv == p.n_qp and min_det > 0.2, (ninv, min_det)
+    w, dx, dv = rng.standard_normal(X.shape), rng.standard_normal(X.shape) * 0.02, rng.standard_normal(X.shape)
+    say("reflected", p.name, "damped", damped, "min |det F|", min_det)
+    m = mesh_of(p)
+    th_d = to_dev(p.theta_all())
+    xd, vd = to_dev(x), to_dev(v)
+    vo = v if damped else None
+    assert rel(to_host(m.internal_force(xd, vd, th_d)), O.internal_force(X, p.blocks, x, vo)) <= TOL
+    rx, rv, rt = O.vjp(X, p.blocks, x, v, w)
+    gx, gv, gt = m.vjp(xd, vd, to_dev(w), th_d)
+    assert rel(to_host(gx), rx) <= TOL
+    if damped:
+        assert rel(to_host(gv), rv) <= TOL
+    gt = to_host(gt)
+    for r in range(5):
+        if np.abs(rt[r]).max() > 0:
+            assert rel(gt[r], rt[r]) <= TOL, r
+    gx2, _, _ = m.vjp(xd, vd, to_dev(w), th_d, want_theta=False)
+    assert rel(to_host(gx2), rx) <= TOL
+    df = to_host(m.jvp(xd, vd, to_dev(dx), to_dev(dv), th_d))
+    assert rel(df, O.jvp(X, p.blocks, x, v, dx, dv if damped else np.zeros_like(dv))) <= TOL
+
+
 @pytest.mark.parametrize("elem", [synth.T10, synth.H8], ids=["T10", "H8"])
 def test_outputs_unchanged_by_exact_translation(elem):
     # Positions enter only through differences against each tile's
