@@ -88,6 +88,37 @@ def test_q27_jvp_matches_oracle(case):
     assert rel(dfth, O.internal_force(q.X, q.blocks, q.x, q.v)) <= TOL
 
 
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_q27_reflected_state(case):
+    """Every point inverted (the mirror image of the state, det F near -1):
+    forward, adjoint with and without the parameter gradients, and tangent
+    against the oracle."""
+    law, damped = case
+    p = q27_problem(law, damped, n=(3, 3, 2), seed=50, per_elem=True)
+    p.x = p.x * np.array([[1.0], [-1.0], [1.0]])
+    ninv, min_det = O.count_inverted(p.X, p.blocks, p.x)
+    assert ninv == p.n_qp and min_det > 0.2, (ninv, min_det)
+    say("q27 reflected", p.name, "min |det F|", min_det)
+    m = mesh_of(p)
+    th = to_dev(p.theta_all())
+    xd, vd = to_dev(p.x), (to_dev(p.v) if damped else None)
+    assert rel(to_host(m.internal_force(xd, vd, th)), O.internal_force(*oc(p), p.v)) <= TOL
+    rx, rv, rt = O.vjp(*oc(p), p.v, p.w)
+    for want_theta in (False, True):
+        gx, gv, gt = m.vjp(xd, vd, to_dev(p.w), th, want_theta=want_theta)
+        assert rel(to_host(gx), rx) <= TOL
+        if damped:
+            assert rel(to_host(gv), rv) <= TOL
+        if want_theta:
+            gt = to_host(gt)
+            for r in range(5):
+                if np.abs(rt[r]).max() > 0:
+                    assert rel(gt[r], rt[r]) <= TOL, r
+    dv = p.dv if damped else None
+    df = to_host(m.jvp(xd, vd, to_dev(p.dx), None if dv is None else to_dev(dv), th))
+    assert rel(df, O.jvp(*oc(p), p.v, p.dx, dv)) <= TOL
+
+
 @pytest.mark.parametrize("damped", [False, True], ids=["el", "KV"])
 def test_q27_mass_step_and_newton_operator_match_oracle(damped):
     p = q27_problem("NH", damped, n=(4, 4, 3), seed=40, per_elem=True)
